@@ -1,0 +1,213 @@
+/*
+ * gw.h -- C ABI of the MI355X density-fitted GW hot path (libgw.so).
+ *
+ * The library evaluates the dynamical GW self-energy of a periodic solid in a
+ * Gaussian Bloch-orbital basis with density-fitted Coulomb integrals, after
+ * Yeh, Iskakov, Zgid and Gull, "Fully self-consistent finite-temperature GW
+ * in Gaussian Bloch orbitals for solids" (Sec. III and Algorithm 1), together
+ * with the imaginary-time / Matsubara transforms, the Hartree-Fock part, the
+ * Dyson equation and the chemical-potential search of the scGW loop (Sec. IV.A).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pointers.  Unless a parameter says "host", an array pointer is a DEVICE
+ *   pointer owned by the caller; the library never frees it.  Complex numbers
+ *   are interleaved (re, im) doubles (gw_z).  Arrays are row-major:
+ *     G, Sigma~, X_tau      [tau][k][i][j]           (ntau, Nk, nao, nao)
+ *     G(iw), Sigma~(iw)     [n][k][i][j]             (nw_f, Nk, nao, nao)
+ *     V                     [q][k][Q][i][j] = V^{k,k+q}_{ij}(Q)  (Nk, Nk, naux, nao, nao)
+ *     P0, P~ (tau)          [q][tau][Q][Q']          (nq, ntau, naux, naux)
+ *     P0, P~ (i Omega)      [q][m][Q][Q']            (nq, nw_b, naux, naux)
+ *     H0, S, Sigma_inf      [k][i][j]                (Nk, nao, nao)
+ *   k = (i1 * n2 + i2) * n3 + i3 on a Gamma-centred n1 x n2 x n3 mesh; k+q and
+ *   k-q are taken component-wise modulo the mesh.  V must satisfy
+ *   V^{k2,k1}(Q) = V^{k1,k2}(Q)^dagger (Hermiticity of the Gaussian density
+ *   fitting, Eqs. VijQ-DF_J); the library reads V^{k+q,k} as the conjugate
+ *   transpose of the stored V^{k,k+q}.
+ * Streams.  Every call enqueues its kernels on the hipStream_t given to
+ *   gw_create and returns without waiting, except where a call says that it
+ *   synchronises (gw_screened_W, gw_dyson_G, gw_find_mu and gw_get_grids
+ *   synchronise to report pivots and scalars).
+ * Errors.  Every call returns gw_status.  Argument errors are found on the
+ *   host before anything is launched, and nothing is written.  The text of the
+ *   last error of a context is returned by gw_last_error.  No C++ exception
+ *   crosses this interface.  An empty range (nq = 0, batch = 0 or R = 0) is
+ *   a no-op that accepts NULL arrays.
+ * Memory.  The library owns the context: the dimensions, the grid tables and
+ *   the k+q tables (device copies made by gw_create / gw_build_grids).  All
+ *   other scratch memory is the caller's, handed over by gw_set_workspace and
+ *   sized by gw_workspace_bytes.
+ * Spin.  Spin-restricted: ns (1 or 2) multiplies the polarization, the
+ *   Hartree term and the electron count; exchange and Sigma~ carry no spin sum.
+ */
+#ifndef GW_H
+#define GW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } gw_z;
+
+typedef enum {
+  GW_OK = 0,
+  GW_ERR_ARG = 1,        /* bad dimension, null pointer, out-of-range index  */
+  GW_ERR_DEVICE = 2,     /* a HIP runtime call failed                        */
+  GW_ERR_SINGULAR = 3,   /* a zero pivot in a Dyson solve                    */
+  GW_ERR_NOCONV = 4,     /* mu search did not bracket or converge            */
+  GW_ERR_WORKSPACE = 5,  /* workspace missing or too small                   */
+  GW_ERR_STATE = 6       /* call made before gw_build_grids                  */
+} gw_status;
+
+enum { GW_FERMION = 0, GW_BOSON = 1 };
+
+/* Contraction precision of the polarization and self-energy chains. */
+enum { GW_PREC_FP64 = 0 };
+
+typedef struct {
+  int mesh[3];     /* n1, n2, n3 >= 1; Nk = n1 n2 n3                          */
+  int nao;         /* orbitals per cell, 1..60                                */
+  int naux;        /* auxiliary functions Q, >= 1                             */
+  int ntau;        /* imaginary-time nodes, even, 2..512                      */
+  int nw_f;        /* fermionic sparse frequencies; must equal ntau           */
+  int nw_b;        /* bosonic sparse frequencies; must equal ntau + 1         */
+  int ns;          /* spin factor, 1 or 2                                     */
+  int precision;   /* GW_PREC_*                                               */
+  double beta;     /* inverse temperature (1/Ha), > 0                         */
+} gw_dims;
+
+typedef struct gw_ctx gw_ctx;
+
+/* Create a context bound to the current HIP device and to hip_stream (a
+ * hipStream_t; NULL means the default stream).  Validates d (GW_ERR_ARG).  */
+gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out);
+gw_status gw_destroy(gw_ctx* ctx);
+
+/* Build the discretisation on the host and copy it to the device.
+ *   tau nodes: roots of the Chebyshev polynomial T_ntau mapped to [0, beta],
+ *     mirrored so that tau_{ntau-1-i} = beta - tau_i (G(beta - tau_i) is node
+ *     ntau-1-i).
+ *   transforms: T[n][i] = int_0^beta L_i(tau) exp(i nu_n tau) d tau, L_i the
+ *     Lagrange polynomials of the nodes (Eqs. tau_to_iw and P0t_to_P0w of the
+ *     paper applied to the interpolant); the inverse transforms (Eqs.
+ *     iw_to_tau and Piw_to_Pt) are the least-squares inverses of T.
+ *   frequencies: fermionic omega_n = (2n+1) pi / beta, bosonic Omega_m =
+ *     2 m pi / beta.  nF (nw_f entries) and nB (nw_b entries), host arrays of
+ *     Matsubara indices, may be given; NULL selects them greedily: symmetric
+ *     pairs {n, -n-1} (fermionic) or {0} then {m, -m} (bosonic) among
+ *     0 <= n < 4 ntau, each time the pair whose transform rows keep the
+ *     largest residual after the rows already chosen are projected out
+ *     (ties within a relative 1e-9 go to the smallest n).  Sets are returned
+ *     sorted ascending.
+ *   density row: w_i = L_i(beta), so gamma = -G(beta^-) = -sum_i w_i G(tau_i).
+ * Host-only arithmetic; synchronises once for the uploads.                  */
+gw_status gw_build_grids(gw_ctx* ctx, const long long* nF, const long long* nB);
+
+/* Copy the host tables out (each pointer is a HOST array and may be NULL):
+ * tau[ntau], nF[nw_f], nB[nw_b], TF[nw_f*ntau], TFp[ntau*nw_f],
+ * TB[nw_b*ntau], TBp[ntau*nw_b] (row-major), w[ntau].                       */
+gw_status gw_get_grids(const gw_ctx* ctx, double* tau, long long* nF, long long* nB,
+                       gw_z* TF, gw_z* TFp, gw_z* TB, gw_z* TBp, double* w);
+
+/* Host-only form of gw_build_grids for inspection and testing: builds the
+ * same tables for (beta, ntau) without a context or a GPU.  nF / nB as in
+ * gw_build_grids (NULL selects them); every output is a HOST array of the
+ * size given for gw_get_grids and may be NULL.                              */
+gw_status gw_grids_host(double beta, int ntau, const long long* nF, const long long* nB,
+                        double* tau, long long* nF_out, long long* nB_out, gw_z* TF, gw_z* TFp,
+                        gw_z* TB, gw_z* TBp, double* w);
+
+/* Workspace.  gw_workspace_bytes returns the bytes a call needs: op is one of
+ * GW_OP_*; for the chains, tau_chunk (1..ntau) is how many tau nodes are
+ * processed per pass (memory grows linearly with it); for GW_OP_SCREENED_W,
+ * tau_chunk is read as nq.  gw_set_workspace hands over a device buffer
+ * (caller-owned, >= 256-byte aligned) and the tau chunk to use; calls that
+ * need more than that buffer return GW_ERR_WORKSPACE.                       */
+enum { GW_OP_POLARIZATION = 0, GW_OP_SELF_ENERGY = 1, GW_OP_SCREENED_W = 2, GW_OP_HF = 3 };
+size_t gw_workspace_bytes(const gw_ctx* ctx, int op, int tau_chunk);
+gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
+
+/* Eq. tilde_P0_tau (reading: G(-tau) of the bubble is the stored G(beta -
+ * tau), sign chosen so that the static bubble is negative semidefinite):
+ *   P0^q_{QQ'}(tau_i) = -(ns/Nk) sum_k sum_{abcd} V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_i)
+ *                       V^{k+q,k}_{bc}(Q') G^k_{cd}(tau_{ntau-1-i})
+ * for q = q0 .. q0+nq-1, written to P0_tau[q-q0][i] (overwritten).          */
+gw_status gw_polarization(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, int q0, int nq,
+                          gw_z* P0_tau);
+
+/* Eqs. tau_to_iw / P0t_to_P0w: X_iw[b][n][r] = sum_i T[n][i] X_tau[b][i][r]
+ * for b < batch, r < R, with T the fermionic (stat = GW_FERMION, nw = nw_f)
+ * or bosonic (GW_BOSON, nw = nw_b) transform.  X_iw is overwritten.          */
+gw_status gw_tau_to_iw(gw_ctx* ctx, int stat, const gw_z* X_tau, long long batch, long long R,
+                       gw_z* X_iw);
+
+/* Eqs. iw_to_tau / Piw_to_Pt as least-squares fits:
+ * X_tau[b][i][r] = sum_n Tp[i][n] X_iw[b][n][r].                            */
+gw_status gw_iw_to_tau(gw_ctx* ctx, int stat, const gw_z* X_iw, long long batch, long long R,
+                       gw_z* X_tau);
+
+/* Eq. tilde_P_omega with I the identity: for each of the nq * nw_b matrices,
+ * Pt_iw = [I - P0_iw]^{-1} P0_iw, by LU with partial pivoting (never by the
+ * geometric series).  Pt_iw may not alias P0_iw.  Synchronises; a zero pivot
+ * returns GW_ERR_SINGULAR (the outputs are then undefined).                  */
+gw_status gw_screened_W(gw_ctx* ctx, const gw_z* P0_iw, int nq, gw_z* Pt_iw);
+
+/* Eq. tilde_sigma2, ACCUMULATED over q = q0 .. q0+nq-1 (Pt_tau[q-q0] holds
+ * P~^q(tau)):
+ *   Sig_tau^k_{ij}(tau) += -(1/Nk) sum_q sum_{ab} sum_{QQ'} G^{k-q}_{ab}(tau)
+ *                          V^{k,k-q}_{ia}(Q) P~^q_{QQ'}(tau) V^{k-q,k}_{bj}(Q')
+ * Callers zero Sig_tau before the first q-batch.                            */
+gw_status gw_self_energy(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* Pt_tau,
+                         int q0, int nq, gw_z* Sig_tau);
+
+/* Density matrix and electron count (Sec. III): gamma^k = -G^k(beta^-) =
+ * -sum_i w_i G^k(tau_i); N_e = (ns/Nk) sum_k Re tr[gamma^k S^k].  gamma is a
+ * device array [k][i][j]; n_out (host, may be NULL) synchronises.            */
+gw_status gw_density(gw_ctx* ctx, const gw_z* G_tau, const gw_z* S, gw_z* gamma, double* n_out);
+
+/* Eqs. HF_J and HF_K with gamma^k = -G^k(beta^-):
+ *   J^k = sum_Q v_Q V^{kk}(Q),  v_Q = (ns/Nk) sum_k' tr[gamma^k' V^{k'k'}(Q)]
+ *   K^k = -(1/Nk) sum_q sum_Q V^{k,k+q}(Q) gamma^{k+q} V^{k+q,k}(Q)
+ * Sig_inf = J + K is overwritten; gamma (may be NULL) receives gamma.        */
+gw_status gw_hf(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, gw_z* gamma, gw_z* Sig_inf);
+
+/* Eq. Dyson: G^k(i w_n) = [(i w_n + mu) S^k - H0^k - Sig_inf^k - Sig_iw^k(i w_n)]^{-1}
+ * for every sparse fermionic n and every k, by Gauss-Jordan elimination with
+ * partial pivoting.  Sig_inf and Sig_iw may be NULL (zero).  Synchronises; a
+ * zero pivot returns GW_ERR_SINGULAR.                                       */
+gw_status gw_dyson_G(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig_inf,
+                     const gw_z* Sig_iw, double mu, gw_z* G_iw);
+
+/* Chemical potential for a fixed electron count (Sec. IV.A): bisection on
+ * N_e(mu) = n_target, N_e from gw_dyson_G and gamma = -G(beta^-).  The bracket
+ * starts at *mu_inout +/- 1 Ha and doubles outward until it holds the root;
+ * bisection stops when it is narrower than tol (Ha; tol <= 0 means 1e-13).
+ * On return *mu_inout is the midpoint, G_iw (may be NULL) holds G at that mu,
+ * G_tau (may be NULL) its transform to the tau nodes, *n_out (may be NULL)
+ * the electron count there.  n_target outside (0, ns*nao) is GW_ERR_ARG; a
+ * bracket that cannot be found is GW_ERR_NOCONV.  Synchronises.             */
+gw_status gw_find_mu(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig_inf,
+                     const gw_z* Sig_iw, double n_target, double tol, double* mu_inout,
+                     gw_z* G_iw, gw_z* G_tau, double* n_out);
+
+/* Damped update and convergence measure of the scGW loop (Sec. IV.A):
+ * Y <- (1 - alpha) Y + alpha X_new over n complex elements.  X_new may be
+ * NULL, in which case Y <- (1 - alpha) Y, and alpha = 1 writes zeros without
+ * reading Y.  maxdiff (host, may be NULL) receives max_i |X_new[i] - Y_old[i]|
+ * (max |Y_old[i]| when X_new is NULL) and makes the call synchronise.       */
+gw_status gw_mix(gw_ctx* ctx, long long n, double alpha, const gw_z* X_new, gw_z* Y,
+                 double* maxdiff);
+
+/* Block until every call enqueued on the context's stream has finished. */
+gw_status gw_synchronize(gw_ctx* ctx);
+
+const char* gw_status_string(gw_status s);
+const char* gw_last_error(const gw_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GW_H */

@@ -1,0 +1,754 @@
+// C ABI of the density-fitted GW hot path: context, argument checks, and the
+// mapping of every equation onto the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gw.h"
+#include "grids.h"
+#include "gw_kernels.h"
+
+struct gw_ctx {
+  gw_dims d;
+  int nk = 0;
+  long long n2 = 0;      // nao^2
+  long long sv = 0;      // complex elements of one V^{k,k+q} block: naux * nao^2
+  hipStream_t st = nullptr;
+  int device = 0;
+  bool grids = false;
+  std::vector<double> tau, x, w;
+  std::vector<long long> nF, nB;
+  std::vector<gwgrid::cd> TF, TFp, TB, TBp, rrow;
+  std::vector<int> plus;   // host copy of the k+q table
+  bool check_bounds = false;
+  double2 *dTF = nullptr, *dTFp = nullptr, *dTB = nullptr, *dTBp = nullptr;
+  double2 *dw = nullptr, *drrow = nullptr;
+  double* dwF = nullptr;
+  int *dplus = nullptr, *dminus = nullptr;
+  int* dflag = nullptr;
+  double* dpart = nullptr;   // nw_f * nk partials, then the reduced scalar at [nw_f*nk]
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int tc = 0;
+  std::string err;
+};
+
+namespace {
+
+gw_status fail(gw_ctx* c, gw_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, GW_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int mesh_index(const int* mesh, int a, int b, int c) {
+  a = ((a % mesh[0]) + mesh[0]) % mesh[0];
+  b = ((b % mesh[1]) + mesh[1]) % mesh[1];
+  c = ((c % mesh[2]) + mesh[2]) % mesh[2];
+  return (a * mesh[1] + b) * mesh[2] + c;
+}
+
+gw_status check_dims(const gw_dims* d, std::string& why) {
+  if (!d) { why = "dims is NULL"; return GW_ERR_ARG; }
+  for (int i = 0; i < 3; ++i)
+    if (d->mesh[i] < 1 || d->mesh[i] > 64) { why = "mesh entries must be in 1..64"; return GW_ERR_ARG; }
+  if (d->nao < 1 || d->nao > 60) { why = "nao must be in 1..60"; return GW_ERR_ARG; }
+  if (d->naux < 1 || d->naux > 8192) { why = "naux must be in 1..8192"; return GW_ERR_ARG; }
+  if (d->ntau < 2 || d->ntau > 512 || d->ntau % 2) { why = "ntau must be even, 2..512"; return GW_ERR_ARG; }
+  if (d->nw_f != d->ntau) { why = "nw_f must equal ntau"; return GW_ERR_ARG; }
+  if (d->nw_b != d->ntau + 1) { why = "nw_b must equal ntau + 1"; return GW_ERR_ARG; }
+  if (d->ns != 1 && d->ns != 2) { why = "ns must be 1 or 2"; return GW_ERR_ARG; }
+  if (!(d->beta > 0.0) || !std::isfinite(d->beta)) { why = "beta must be positive"; return GW_ERR_ARG; }
+  if (d->precision != GW_PREC_FP64) { why = "unsupported precision"; return GW_ERR_ARG; }
+  const long long nk = (long long)d->mesh[0] * d->mesh[1] * d->mesh[2];
+  if (nk * d->nao * (long long)d->nao * d->naux > (1LL << 31)) {
+    why = "Nk * naux * nao^2 must stay below 2^31";
+    return GW_ERR_ARG;
+  }
+  return GW_OK;
+}
+
+bool ready(gw_ctx* c) { return c && c->grids; }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+template <class T>
+gw_status upload(gw_ctx* c, T** dst, const void* src, size_t bytes) {
+  HIPCHK(c, hipMalloc((void**)dst, bytes));
+  HIPCHK(c, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return GW_OK;
+}
+
+// Exact [min, max] of a mapped index over i in [0, n).
+void map_range(const Map3& m, long long n, long long& lo, long long& hi) {
+  lo = hi = 0;
+  for (long long i = 0; i < n; ++i) {
+    const unsigned a = (unsigned)(i % m.din);
+    const unsigned r = (unsigned)(i / m.din);
+    const long long o = (long long)(r / m.dmid) * m.sout + (long long)(r % m.dmid) * m.smid +
+                        (long long)a * m.sin;
+    if (i == 0 || o < lo) lo = (i == 0) ? o : std::min(lo, o);
+    if (i == 0 || o > hi) hi = (i == 0) ? o : std::max(hi, o);
+  }
+}
+
+// Host-side proof that a GEMM descriptor stays inside its operands: every
+// touched offset of A, B and C lies in [0, ext).  Enabled by GW_DEBUG_BOUNDS.
+struct Ext {
+  long long lo, hi;   // valid element offsets [lo, hi) relative to the operand pointer
+};
+
+bool gemm_in_bounds(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC, std::string& why) {
+  long long bl[3] = {0, 0, 0}, bh[3] = {0, 0, 0};
+  const Map3* bm[3] = {&g.ba, &g.bb, &g.bc};
+  const long long ts[3] = {g.tsA, g.tsB, g.tsC};
+  for (int o = 0; o < 3; ++o)
+    for (long long b = 0; b < g.batch; ++b) {
+      const unsigned a = (unsigned)(b % bm[o]->din);
+      const unsigned r = (unsigned)(b / bm[o]->din);
+      long long off = (long long)(r / bm[o]->dmid) * bm[o]->sout +
+                      (long long)(r % bm[o]->dmid) * bm[o]->smid + (long long)a * bm[o]->sin;
+      if (ts[o] != 0) {
+        const int tq = (int)(g.tab - c->dplus);          // tables are rows of the k+q table
+        off += (long long)c->plus[(size_t)tq + (size_t)(b % g.tmod)] * ts[o];
+      }
+      if (b == 0 || off < bl[o]) bl[o] = (b == 0) ? off : std::min(bl[o], off);
+      if (b == 0 || off > bh[o]) bh[o] = (b == 0) ? off : std::max(bh[o], off);
+    }
+  long long l1, h1, l2, h2;
+  map_range(g.am, g.M, l1, h1);
+  map_range(g.ak, g.K, l2, h2);
+  if (bl[0] + l1 + l2 < eA.lo || bh[0] + h1 + h2 >= eA.hi) {
+    why = "A out of bounds: [" + std::to_string(bl[0] + l1 + l2) + ", " + std::to_string(bh[0] + h1 + h2) +
+          "] vs [" + std::to_string(eA.lo) + ", " + std::to_string(eA.hi) + ")";
+    return false;
+  }
+  map_range(g.bk, g.K, l1, h1);
+  map_range(g.bn, g.N, l2, h2);
+  if (bl[1] + l1 + l2 < eB.lo || bh[1] + h1 + h2 >= eB.hi) {
+    why = "B out of bounds: [" + std::to_string(bl[1] + l1 + l2) + ", " + std::to_string(bh[1] + h1 + h2) +
+          "] vs [" + std::to_string(eB.lo) + ", " + std::to_string(eB.hi) + ")";
+    return false;
+  }
+  map_range(g.cm, g.M, l1, h1);
+  map_range(g.cn, g.N, l2, h2);
+  if (bl[2] + l1 + l2 < eC.lo || bh[2] + h1 + h2 >= eC.hi) {
+    why = "C out of bounds: [" + std::to_string(bl[2] + l1 + l2) + ", " + std::to_string(bh[2] + h1 + h2) +
+          "] vs [" + std::to_string(eC.lo) + ", " + std::to_string(eC.hi) + ")";
+    return false;
+  }
+  return true;
+}
+
+gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
+  if (c->check_bounds) {
+    std::string why;
+    if (!gemm_in_bounds(c, g, eA, eB, eC, why))
+      return fail(c, GW_ERR_ARG, "internal descriptor check: " + why);
+  }
+  hipError_t e = zgemm_launch(g, c->st);
+  if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("zgemm: ") + hipGetErrorString(e));
+  return GW_OK;
+}
+
+gw_status read_flag(gw_ctx* c, const char* what) {
+  int f = 0;
+  HIPCHK(c, hipMemcpyAsync(&f, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (f) return fail(c, GW_ERR_SINGULAR, std::string(what) + ": zero pivot");
+  return GW_OK;
+}
+
+// Electron count of G at mu (no G written unless Gout is given).
+gw_status count_at(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf, const gw_z* Siw,
+                   double mu, gw_z* Gout, double* ne) {
+  DysonArgs a{};
+  a.H0 = (const double2*)H0;
+  a.S = (const double2*)S;
+  a.Sinf = (const double2*)Sinf;
+  a.Siw = (const double2*)Siw;
+  a.wF = c->dwF;
+  a.rrow = c->drrow;
+  a.mu = mu;
+  a.nk = c->nk;
+  a.nao = c->d.nao;
+  a.G = (double2*)Gout;
+  a.part = c->dpart;
+  a.flag = c->dflag;
+  HIPCHK(c, dyson_launch(a, c->d.nw_f, c->st));
+  const long long np = (long long)c->d.nw_f * c->nk;
+  HIPCHK(c, sum_launch(c->dpart, np, -(double)c->d.ns / c->nk, c->dpart + np, c->st));
+  HIPCHK(c, hipMemcpyAsync(ne, c->dpart + np, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gw_status_string(gw_status s) {
+  switch (s) {
+    case GW_OK: return "ok";
+    case GW_ERR_ARG: return "invalid argument";
+    case GW_ERR_DEVICE: return "HIP runtime error";
+    case GW_ERR_SINGULAR: return "singular matrix";
+    case GW_ERR_NOCONV: return "no convergence";
+    case GW_ERR_WORKSPACE: return "workspace missing or too small";
+    case GW_ERR_STATE: return "grids not built";
+  }
+  return "unknown status";
+}
+
+const char* gw_last_error(const gw_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
+  if (!out) return GW_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  if (check_dims(d, why) != GW_OK) return GW_ERR_ARG;
+  gw_ctx* c = new (std::nothrow) gw_ctx();
+  if (!c) return GW_ERR_DEVICE;
+  c->d = *d;
+  c->nk = d->mesh[0] * d->mesh[1] * d->mesh[2];
+  c->n2 = (long long)d->nao * d->nao;
+  c->sv = (long long)d->naux * c->n2;
+  c->st = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return GW_ERR_DEVICE; }
+  std::vector<int> plus((size_t)c->nk * c->nk), minus((size_t)c->nk * c->nk);
+  const int* m = d->mesh;
+  for (int q = 0; q < c->nk; ++q)
+    for (int k = 0; k < c->nk; ++k) {
+      const int qa = q / (m[1] * m[2]), qb = (q / m[2]) % m[1], qc = q % m[2];
+      const int ka = k / (m[1] * m[2]), kb = (k / m[2]) % m[1], kc = k % m[2];
+      plus[(size_t)q * c->nk + k] = mesh_index(m, ka + qa, kb + qb, kc + qc);
+      minus[(size_t)q * c->nk + k] = mesh_index(m, ka - qa, kb - qb, kc - qc);
+    }
+  c->plus = plus;
+  {
+    const char* e = std::getenv("GW_DEBUG_BOUNDS");
+    c->check_bounds = e && e[0] == '1';
+  }
+  if (upload(c, &c->dplus, plus.data(), plus.size() * sizeof(int)) != GW_OK ||
+      upload(c, &c->dminus, minus.data(), minus.size() * sizeof(int)) != GW_OK ||
+      hipMalloc((void**)&c->dflag, sizeof(int)) != hipSuccess ||
+      hipMemset(c->dflag, 0, sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&c->dpart, ((size_t)d->nw_f * c->nk + 8) * sizeof(double)) != hipSuccess) {
+    gw_destroy(c);
+    return GW_ERR_DEVICE;
+  }
+  *out = c;
+  return GW_OK;
+}
+
+gw_status gw_destroy(gw_ctx* c) {
+  if (!c) return GW_ERR_ARG;
+  void* ptrs[] = {c->dTF, c->dTFp, c->dTB, c->dTBp, c->dw, c->drrow, c->dwF,
+                  c->dplus, c->dminus, c->dflag, c->dpart};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+  return GW_OK;
+}
+
+struct HostGrids {
+  std::vector<double> tau, x, w;
+  std::vector<long long> nF, nB;
+  std::vector<gwgrid::cd> TF, TFp, TB, TBp, rrow;
+  std::vector<double> wf;
+};
+
+static gw_status make_grids(double beta, int nt, const long long* nF, const long long* nB,
+                            HostGrids& g, std::string& why) {
+  if (!(beta > 0.0) || !std::isfinite(beta) || nt < 2 || nt > 512 || nt % 2) {
+    why = "beta must be positive and ntau even in 2..512";
+    return GW_ERR_ARG;
+  }
+  const int nwf = nt, nwb = nt + 1;
+  try {
+    g.tau.assign(nt, 0.0);
+    g.x.assign(nt, 0.0);
+    gwgrid::tau_nodes(beta, nt, g.tau.data(), g.x.data());
+    if (nF) g.nF.assign(nF, nF + nwf); else g.nF = gwgrid::select_sparse(beta, nt, 0);
+    if (nB) g.nB.assign(nB, nB + nwb); else g.nB = gwgrid::select_sparse(beta, nt, 1);
+    for (size_t i = 1; i < g.nF.size(); ++i)
+      if (g.nF[i] <= g.nF[i - 1]) { why = "nF must be strictly increasing"; return GW_ERR_ARG; }
+    for (size_t i = 1; i < g.nB.size(); ++i)
+      if (g.nB[i] <= g.nB[i - 1]) { why = "nB must be strictly increasing"; return GW_ERR_ARG; }
+    g.wf.assign(nwf, 0.0);
+    std::vector<double> wb(nwb);
+    for (int n = 0; n < nwf; ++n) g.wf[n] = gwgrid::matsubara(g.nF[n], beta, 0);
+    for (int n = 0; n < nwb; ++n) wb[n] = gwgrid::matsubara(g.nB[n], beta, 1);
+    g.TF.assign((size_t)nwf * nt, 0.0);
+    g.TB.assign((size_t)nwb * nt, 0.0);
+    g.TFp.assign((size_t)nt * nwf, 0.0);
+    g.TBp.assign((size_t)nt * nwb, 0.0);
+    gwgrid::transform(beta, nt, g.x.data(), g.wf.data(), nwf, g.TF.data());
+    gwgrid::transform(beta, nt, g.x.data(), wb.data(), nwb, g.TB.data());
+    if (gwgrid::pinv_qr(g.TF.data(), nwf, nt, g.TFp.data()) ||
+        gwgrid::pinv_qr(g.TB.data(), nwb, nt, g.TBp.data())) {
+      why = "transform matrix is rank deficient for these frequencies";
+      return GW_ERR_ARG;
+    }
+    g.w.assign(nt, 0.0);
+    gwgrid::beta_row(nt, g.x.data(), g.w.data());
+    g.rrow.assign(nwf, 0.0);
+    for (int n = 0; n < nwf; ++n) {
+      gwgrid::cd s = 0.0;
+      for (int i = 0; i < nt; ++i) s += g.w[i] * g.TFp[(size_t)i * nwf + n];
+      g.rrow[n] = s;
+    }
+  } catch (const std::exception& e) {
+    why = e.what();
+    return GW_ERR_ARG;
+  }
+  return GW_OK;
+}
+
+gw_status gw_grids_host(double beta, int ntau, const long long* nF, const long long* nB,
+                        double* tau, long long* nF_out, long long* nB_out, gw_z* TF, gw_z* TFp,
+                        gw_z* TB, gw_z* TBp, double* w) {
+  HostGrids g;
+  std::string why;
+  gw_status s = make_grids(beta, ntau, nF, nB, g, why);
+  if (s != GW_OK) return s;
+  if (tau) std::memcpy(tau, g.tau.data(), g.tau.size() * 8);
+  if (nF_out) std::memcpy(nF_out, g.nF.data(), g.nF.size() * 8);
+  if (nB_out) std::memcpy(nB_out, g.nB.data(), g.nB.size() * 8);
+  if (TF) std::memcpy(TF, g.TF.data(), g.TF.size() * 16);
+  if (TFp) std::memcpy(TFp, g.TFp.data(), g.TFp.size() * 16);
+  if (TB) std::memcpy(TB, g.TB.data(), g.TB.size() * 16);
+  if (TBp) std::memcpy(TBp, g.TBp.data(), g.TBp.size() * 16);
+  if (w) std::memcpy(w, g.w.data(), g.w.size() * 8);
+  return GW_OK;
+}
+
+gw_status gw_build_grids(gw_ctx* c, const long long* nF, const long long* nB) {
+  if (!c) return GW_ERR_ARG;
+  HostGrids g;
+  std::string why;
+  gw_status s = make_grids(c->d.beta, c->d.ntau, nF, nB, g, why);
+  if (s != GW_OK) return fail(c, s, why);
+  c->tau = g.tau; c->x = g.x; c->w = g.w; c->nF = g.nF; c->nB = g.nB;
+  c->TF = g.TF; c->TFp = g.TFp; c->TB = g.TB; c->TBp = g.TBp; c->rrow = g.rrow;
+  std::vector<gwgrid::cd> wz(c->w.begin(), c->w.end());
+  void* olds[] = {c->dTF, c->dTFp, c->dTB, c->dTBp, c->dw, c->drrow, c->dwF};
+  for (void* p : olds)
+    if (p) (void)hipFree(p);
+  c->dTF = c->dTFp = c->dTB = c->dTBp = c->dw = c->drrow = nullptr;
+  c->dwF = nullptr;
+  c->grids = false;
+  if ((s = upload(c, &c->dTF, c->TF.data(), c->TF.size() * 16)) != GW_OK) return s;
+  if ((s = upload(c, &c->dTFp, c->TFp.data(), c->TFp.size() * 16)) != GW_OK) return s;
+  if ((s = upload(c, &c->dTB, c->TB.data(), c->TB.size() * 16)) != GW_OK) return s;
+  if ((s = upload(c, &c->dTBp, c->TBp.data(), c->TBp.size() * 16)) != GW_OK) return s;
+  if ((s = upload(c, &c->dw, wz.data(), wz.size() * 16)) != GW_OK) return s;
+  if ((s = upload(c, &c->drrow, c->rrow.data(), c->rrow.size() * 16)) != GW_OK) return s;
+  if ((s = upload(c, &c->dwF, g.wf.data(), g.wf.size() * 8)) != GW_OK) return s;
+  c->grids = true;
+  return GW_OK;
+}
+
+gw_status gw_get_grids(const gw_ctx* cc, double* tau, long long* nF, long long* nB, gw_z* TF,
+                       gw_z* TFp, gw_z* TB, gw_z* TBp, double* w) {
+  gw_ctx* c = const_cast<gw_ctx*>(cc);
+  if (!c) return GW_ERR_ARG;
+  if (!c->grids) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (tau) std::memcpy(tau, c->tau.data(), c->tau.size() * 8);
+  if (nF) std::memcpy(nF, c->nF.data(), c->nF.size() * 8);
+  if (nB) std::memcpy(nB, c->nB.data(), c->nB.size() * 8);
+  if (TF) std::memcpy(TF, c->TF.data(), c->TF.size() * 16);
+  if (TFp) std::memcpy(TFp, c->TFp.data(), c->TFp.size() * 16);
+  if (TB) std::memcpy(TB, c->TB.data(), c->TB.size() * 16);
+  if (TBp) std::memcpy(TBp, c->TBp.data(), c->TBp.size() * 16);
+  if (w) std::memcpy(w, c->w.data(), c->w.size() * 8);
+  return GW_OK;
+}
+
+size_t gw_workspace_bytes(const gw_ctx* c, int op, int tau_chunk) {
+  if (!c) return 0;
+  const size_t z = 16;
+  switch (op) {
+    case GW_OP_POLARIZATION:
+    case GW_OP_SELF_ENERGY:
+      if (tau_chunk < 1 || tau_chunk > c->d.ntau) return 0;
+      return 2 * align256((size_t)tau_chunk * c->nk * c->sv * z);
+    case GW_OP_SCREENED_W:
+      if (tau_chunk < 1) return 0;
+      return align256((size_t)tau_chunk * c->d.nw_b * c->d.naux * (size_t)c->d.naux * z);
+    case GW_OP_HF:
+      return align256((size_t)c->nk * c->sv * z) + align256((size_t)c->nk * c->n2 * z) +
+             align256((size_t)c->d.naux * z);
+  }
+  return 0;
+}
+
+gw_status gw_set_workspace(gw_ctx* c, void* dev, size_t bytes, int tau_chunk) {
+  if (!c) return GW_ERR_ARG;
+  if (tau_chunk < 1 || tau_chunk > c->d.ntau)
+    return fail(c, GW_ERR_ARG, "tau_chunk must be in 1..ntau");
+  if (bytes && !dev) return fail(c, GW_ERR_ARG, "workspace pointer is NULL");
+  if (((uintptr_t)dev) & 255) return fail(c, GW_ERR_ARG, "workspace must be 256-byte aligned");
+  c->ws = dev;
+  c->ws_bytes = bytes;
+  c->tc = tau_chunk;
+  return GW_OK;
+}
+
+gw_status gw_mix(gw_ctx* c, long long n, double alpha, const gw_z* X, gw_z* Y, double* maxdiff) {
+  if (!c) return GW_ERR_ARG;
+  if (!Y || n < 0) return fail(c, GW_ERR_ARG, "bad gw_mix arguments");
+  if (!std::isfinite(alpha)) return fail(c, GW_ERR_ARG, "alpha is not finite");
+  if (n == 0) {
+    if (maxdiff) *maxdiff = 0.0;
+    return GW_OK;
+  }
+  // partial maxima reuse the electron-count scratch (nw_f * nk + 8 doubles)
+  const int cap = c->d.nw_f * c->nk + 7;
+  const int nblk = (int)std::max(1LL, std::min<long long>({(n + 255) / 256, 2048LL, (long long)cap - 1}));
+  HIPCHK(c, mix_launch(n, alpha, (const double2*)X, (double2*)Y, maxdiff ? c->dpart : nullptr, nblk,
+                       c->st));
+  if (maxdiff) {
+    HIPCHK(c, hipMemcpyAsync(maxdiff, c->dpart + nblk, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  return GW_OK;
+}
+
+gw_status gw_synchronize(gw_ctx* c) {
+  if (!c) return GW_ERR_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GW_OK;
+}
+
+// ------------------------------------------------------------- Eq. tilde_P0_tau
+gw_status gw_polarization(gw_ctx* c, const gw_z* V, const gw_z* G, int q0, int nq, gw_z* P0) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
+  if (nq == 0) return GW_OK;
+  if (!V || !G || !P0) return fail(c, GW_ERR_ARG, "NULL array");
+  const int tc = c->tc;
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_POLARIZATION, tc))
+    return fail(c, GW_ERR_WORKSPACE, "polarization workspace too small");
+  const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
+  const long long n2 = c->n2, sv = c->sv;
+  const long long S = (long long)nk * sv;                // one tau slice of X or Zt
+  double2* X = (double2*)c->ws;
+  double2* Z = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
+  const double2* Vd = (const double2*)V;
+  const double2* Gd = (const double2*)G;
+  for (int q = q0; q < q0 + nq; ++q) {
+    for (int t0 = 0; t0 < nt; t0 += tc) {
+      const int tcur = std::min(tc, nt - t0);
+      // X[tl][k][Q][d][b] = sum_a V[q][k][Q][d][a] G[t0+tl][k+q][a][b]
+      const double2* Aq = Vd + (long long)q * nk * sv;
+      GemmDesc g = gemm_desc();
+      g.A = Aq; g.B = Gd + (long long)t0 * nk * n2; g.C = X;
+      g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
+      g.am = aff(nao); g.ak = aff(1);
+      g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
+      g.cm = aff(nao); g.cn = two(nao, 1, S);
+      g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
+      g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;   // G^{k+q}
+      gw_status s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * S});
+      if (s != GW_OK) return s;
+      // Zt[tl][k][Q'][d][b] = sum_c G[nt-1-t0-tl][k][c][d] conj(V[q][k][Q'][c][b])
+      g = gemm_desc();
+      g.A = Gd + (long long)(nt - 1 - t0) * nk * n2; g.B = Aq; g.C = Z;
+      g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
+      g.am = two(nao, 1, -(long long)nk * n2); g.ak = aff(nao);
+      g.bk = aff(nao); g.bn = two(nao, 1, n2); g.conjB = 1;
+      g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
+      g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
+      if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tc * S})) != GW_OK) return s;
+      // P0[q-q0][t0+tl][Q][Q'] = -(ns/nk) sum_{k,e} X[tl][k][Q][e] Zt[tl][k][Q'][e]
+      g = gemm_desc();
+      g.A = X; g.B = Z; g.C = (double2*)P0 + ((long long)(q - q0) * nt + t0) * naux * naux;
+      g.M = naux; g.N = naux; g.K = nk * (int)n2; g.batch = tcur;
+      g.am = aff(n2); g.ak = two((unsigned)n2, 1, sv);
+      g.bk = two((unsigned)n2, 1, sv); g.bn = aff(n2);
+      g.cm = aff(naux); g.cn = aff(1);
+      g.ba = aff(S); g.bb = aff(S); g.bc = aff((long long)naux * naux);
+      g.alpha_r = -(double)c->d.ns / nk;
+      if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * naux * naux})) != GW_OK) return s;
+    }
+  }
+  return GW_OK;
+}
+
+// ------------------------------------------------------------- transforms
+static gw_status transform(gw_ctx* c, int stat, const gw_z* Xin, long long batch, long long R,
+                           gw_z* Xout, bool forward) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (stat != GW_FERMION && stat != GW_BOSON) return fail(c, GW_ERR_ARG, "stat must be 0 or 1");
+  if (batch < 0 || R < 0 || batch > 65535 || R > 0x7fffffffLL)
+    return fail(c, GW_ERR_ARG, "batch or R out of range");
+  if (batch == 0 || R == 0) return GW_OK;
+  if (!Xin || !Xout) return fail(c, GW_ERR_ARG, "NULL array");
+  const int nt = c->d.ntau;
+  const int nw = stat == GW_FERMION ? c->d.nw_f : c->d.nw_b;
+  const int rows = forward ? nw : nt, inner = forward ? nt : nw;
+  GemmDesc g = gemm_desc();
+  g.A = forward ? (stat == GW_FERMION ? c->dTF : c->dTB) : (stat == GW_FERMION ? c->dTFp : c->dTBp);
+  g.B = (const double2*)Xin;
+  g.C = (double2*)Xout;
+  g.M = rows; g.N = (int)R; g.K = inner; g.batch = (int)batch;
+  g.am = aff(inner); g.ak = aff(1);
+  g.bk = aff(R); g.bn = aff(1);
+  g.cm = aff(R); g.cn = aff(1);
+  g.ba = aff(0); g.bb = aff((long long)inner * R); g.bc = aff((long long)rows * R);
+  return run(c, g, Ext{0, (long long)rows * inner}, Ext{0, batch * inner * R}, Ext{0, batch * rows * R});
+}
+
+gw_status gw_tau_to_iw(gw_ctx* c, int stat, const gw_z* X_tau, long long batch, long long R,
+                       gw_z* X_iw) {
+  return transform(c, stat, X_tau, batch, R, X_iw, true);
+}
+
+gw_status gw_iw_to_tau(gw_ctx* c, int stat, const gw_z* X_iw, long long batch, long long R,
+                       gw_z* X_tau) {
+  return transform(c, stat, X_iw, batch, R, X_tau, false);
+}
+
+// ------------------------------------------------------------- Eq. tilde_P_omega
+gw_status gw_screened_W(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (nq < 0 || nq > c->nk) return fail(c, GW_ERR_ARG, "nq out of range");
+  if (nq == 0) return GW_OK;
+  if (!P0 || !Pt) return fail(c, GW_ERR_ARG, "NULL array");
+  if (P0 == Pt) return fail(c, GW_ERR_ARG, "Pt_iw may not alias P0_iw");
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_SCREENED_W, nq))
+    return fail(c, GW_ERR_WORKSPACE, "screened_W workspace too small");
+  HIPCHK(c, zero_flag_launch(c->dflag, c->st));
+  HIPCHK(c, wdyson_launch((const double2*)P0, (double2*)Pt, (double2*)c->ws, c->d.naux,
+                          (long long)nq * c->d.nw_b, c->dflag, c->st));
+  return read_flag(c, "screened_W");
+}
+
+// ------------------------------------------------------------- Eq. tilde_sigma2
+gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt, int q0, int nq,
+                         gw_z* Sig) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
+  if (nq == 0) return GW_OK;
+  if (!V || !G || !Pt || !Sig) return fail(c, GW_ERR_ARG, "NULL array");
+  const int tc = c->tc;
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_SELF_ENERGY, tc))
+    return fail(c, GW_ERR_WORKSPACE, "self-energy workspace too small");
+  const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
+  const long long n2 = c->n2, sv = c->sv;
+  const long long S = (long long)nk * sv;
+  double2* Vt = (double2*)c->ws;
+  double2* L = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
+  const double2* Vd = (const double2*)V;
+  const double2* Gd = (const double2*)G;
+  for (int q = q0; q < q0 + nq; ++q) {
+    const double2* Aq = Vd + (long long)q * nk * sv;
+    for (int t0 = 0; t0 < nt; t0 += tc) {
+      const int tcur = std::min(tc, nt - t0);
+      // Vt[tl][Q][kk][b][j] = sum_Q' Pt[q][t0+tl][Q][Q'] V[q][kk][Q'][b][j]
+      GemmDesc g = gemm_desc();
+      g.A = (const double2*)Pt + ((long long)(q - q0) * nt + t0) * naux * naux;
+      g.B = Aq; g.C = Vt;
+      g.M = naux; g.N = nk * (int)n2; g.K = naux; g.batch = tcur;
+      g.am = aff(naux); g.ak = aff(1);
+      g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
+      g.cm = aff((long long)nk * n2); g.cn = aff(1);
+      g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
+      gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
+      if (s != GW_OK) return s;
+      // L[tl][kk][Q][i][b] = sum_a conj(V[q][kk][Q][a][i]) G[t0+tl][kk][a][b]
+      g = gemm_desc();
+      g.A = Aq; g.B = Gd + (long long)t0 * nk * n2; g.C = L;
+      g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
+      g.am = two(nao, 1, n2); g.ak = aff(nao); g.conjA = 1;
+      g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
+      g.cm = aff(nao); g.cn = two(nao, 1, S);
+      g.ba = aff(sv); g.bb = aff(n2); g.bc = aff(sv);
+      if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
+      // Sig[t0+tl][kk+q][i][j] += -(1/nk) sum_{Q,b} L[tl][kk][Q][i][b] Vt[tl][Q][kk][b][j]
+      g = gemm_desc();
+      g.A = L; g.B = Vt; g.C = (double2*)Sig + (long long)t0 * nk * n2;
+      g.M = nao; g.N = nao; g.K = naux * nao; g.batch = tcur * nk;
+      g.am = aff(nao); g.ak = two(nao, 1, n2);
+      g.bk = two(nao, nao, (long long)nk * n2); g.bn = aff(1);
+      g.cm = aff(nao); g.cn = aff(1);
+      g.ba = two(nk, sv, S); g.bb = two(nk, n2, S); g.bc = two(nk, 0, (long long)nk * n2);
+      g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
+      g.alpha_r = -1.0 / nk;
+      g.beta_zero = 0; g.beta_r = 1.0;
+      if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * nk * n2})) != GW_OK) return s;
+    }
+  }
+  return GW_OK;
+}
+
+// ------------------------------------------------------------- density
+static gw_status gamma_of(gw_ctx* c, const gw_z* G, double2* gamma) {
+  GemmDesc g = gemm_desc();
+  g.A = c->dw; g.B = (const double2*)G; g.C = gamma;
+  g.M = 1; g.N = c->nk * (int)c->n2; g.K = c->d.ntau;
+  g.am = aff(0); g.ak = aff(1); g.bk = aff((long long)c->nk * c->n2); g.bn = aff(1);
+  g.cm = aff(0); g.cn = aff(1);
+  g.alpha_r = -1.0;
+  return run(c, g, Ext{0, (long long)c->d.ntau}, Ext{0, (long long)c->d.ntau * c->nk * c->n2}, Ext{0, (long long)c->nk * c->n2});
+}
+
+gw_status gw_density(gw_ctx* c, const gw_z* G, const gw_z* S, gw_z* gamma, double* n_out) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!G || !gamma || (n_out && !S)) return fail(c, GW_ERR_ARG, "NULL array");
+  gw_status s = gamma_of(c, G, (double2*)gamma);
+  if (s != GW_OK || !n_out) return s;
+  HIPCHK(c, trace_launch((const double2*)gamma, (const double2*)S, c->d.nao, c->nk, c->dpart, c->st));
+  HIPCHK(c, sum_launch(c->dpart, c->nk, (double)c->d.ns / c->nk, c->dpart + c->nk, c->st));
+  HIPCHK(c, hipMemcpyAsync(n_out, c->dpart + c->nk, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GW_OK;
+}
+
+// ------------------------------------------------------------- Eqs. HF_J, HF_K
+gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* Sinf) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!V || !G || !Sinf) return fail(c, GW_ERR_ARG, "NULL array");
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_HF, 1))
+    return fail(c, GW_ERR_WORKSPACE, "HF workspace too small");
+  const int nk = c->nk, nao = c->d.nao, naux = c->d.naux;
+  const long long n2 = c->n2, sv = c->sv;
+  double2* T1 = (double2*)c->ws;
+  double2* gam = (double2*)((char*)c->ws + align256((size_t)nk * sv * 16));
+  double2* vq = (double2*)((char*)gam + align256((size_t)nk * n2 * 16));
+  if (gamma_out) gam = (double2*)gamma_out;
+  const double2* Vd = (const double2*)V;
+  gw_status s = gamma_of(c, G, gam);
+  if (s != GW_OK) return s;
+  // v[Q] = (ns/nk) sum_{k',b,a} V[0][k'][Q][b][a] gamma[k'][a][b]
+  GemmDesc g = gemm_desc();
+  g.A = Vd; g.B = gam; g.C = vq;
+  g.M = naux; g.N = 1; g.K = nk * (int)n2;
+  g.am = aff(n2); g.ak = two((unsigned)n2, 1, sv);
+  g.bk = three(nao, nao, nao, 1, n2); g.bn = aff(0);
+  g.cm = aff(1); g.cn = aff(0);
+  g.alpha_r = (double)c->d.ns / nk;
+  if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)naux})) != GW_OK) return s;
+  // J[k][e] = sum_Q v[Q] V[0][k][Q][e]
+  g = gemm_desc();
+  g.A = vq; g.B = Vd; g.C = (double2*)Sinf;
+  g.M = 1; g.N = nk * (int)n2; g.K = naux;
+  g.am = aff(0); g.ak = aff(1);
+  g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
+  g.cm = aff(0); g.cn = aff(1);
+  if ((s = run(c, g, Ext{0, (long long)naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
+  for (int q = 0; q < nk; ++q) {
+    const double2* Aq = Vd + (long long)q * nk * sv;
+    // T1[k][Q][i][b] = sum_a V[q][k][Q][i][a] gamma[k+q][a][b]
+    g = gemm_desc();
+    g.A = Aq; g.B = gam; g.C = T1;
+    g.M = naux * nao; g.N = nao; g.K = nao; g.batch = nk;
+    g.am = aff(nao); g.ak = aff(1); g.bk = aff(nao); g.bn = aff(1);
+    g.cm = aff(nao); g.cn = aff(1);
+    g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
+    g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;
+    if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)nk * sv})) != GW_OK) return s;
+    // Sinf[k][i][j] += -(1/nk) sum_{Q,b} T1[k][Q][i][b] conj(V[q][k][Q][j][b])
+    g = gemm_desc();
+    g.A = T1; g.B = Aq; g.C = (double2*)Sinf;
+    g.M = nao; g.N = nao; g.K = naux * nao; g.batch = nk;
+    g.am = aff(nao); g.ak = two(nao, 1, n2);
+    g.bk = two(nao, 1, n2); g.bn = aff(nao); g.conjB = 1;
+    g.cm = aff(nao); g.cn = aff(1);
+    g.ba = aff(sv); g.bb = aff(sv); g.bc = aff(n2);
+    g.alpha_r = -1.0 / nk;
+    g.beta_zero = 0; g.beta_r = 1.0;
+    if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
+  }
+  return GW_OK;
+}
+
+// ------------------------------------------------------------- Eq. Dyson
+gw_status gw_dyson_G(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf, const gw_z* Siw,
+                     double mu, gw_z* G) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!H0 || !S || !G) return fail(c, GW_ERR_ARG, "NULL array");
+  if (!std::isfinite(mu)) return fail(c, GW_ERR_ARG, "mu is not finite");
+  HIPCHK(c, zero_flag_launch(c->dflag, c->st));
+  DysonArgs a{};
+  a.H0 = (const double2*)H0; a.S = (const double2*)S;
+  a.Sinf = (const double2*)Sinf; a.Siw = (const double2*)Siw;
+  a.wF = c->dwF; a.rrow = c->drrow; a.mu = mu; a.nk = c->nk; a.nao = c->d.nao;
+  a.G = (double2*)G; a.part = nullptr; a.flag = c->dflag;
+  HIPCHK(c, dyson_launch(a, c->d.nw_f, c->st));
+  return read_flag(c, "dyson_G");
+}
+
+gw_status gw_find_mu(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf, const gw_z* Siw,
+                     double n_target, double tol, double* mu_inout, gw_z* G_iw, gw_z* G_tau,
+                     double* n_out) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!H0 || !S || !mu_inout) return fail(c, GW_ERR_ARG, "NULL array");
+  if (G_tau && !G_iw) return fail(c, GW_ERR_ARG, "G_tau needs G_iw");
+  if (!(n_target > 0.0) || !(n_target < (double)c->d.ns * c->d.nao))
+    return fail(c, GW_ERR_ARG, "n_target must lie in (0, ns*nao)");
+  if (!std::isfinite(*mu_inout)) return fail(c, GW_ERR_ARG, "initial mu is not finite");
+  if (!(tol > 0.0)) tol = 1e-13;
+  HIPCHK(c, zero_flag_launch(c->dflag, c->st));
+  const double mu0 = *mu_inout;
+  double lo = mu0 - 1.0, hi = mu0 + 1.0, n = 0.0, step = 1.0;
+  gw_status s;
+  int it = 0;
+  for (;;) {
+    if ((s = count_at(c, H0, S, Sinf, Siw, lo, nullptr, &n)) != GW_OK) return s;
+    if (!(n > n_target)) break;
+    step *= 2.0;
+    lo -= step;
+    if (++it > 60) return fail(c, GW_ERR_NOCONV, "mu search: no lower bracket");
+  }
+  step = 1.0;
+  it = 0;
+  for (;;) {
+    if ((s = count_at(c, H0, S, Sinf, Siw, hi, nullptr, &n)) != GW_OK) return s;
+    if (!(n < n_target)) break;
+    step *= 2.0;
+    hi += step;
+    if (++it > 60) return fail(c, GW_ERR_NOCONV, "mu search: no upper bracket");
+  }
+  it = 0;
+  while (hi - lo > tol && it < 400) {
+    const double mid = 0.5 * (lo + hi);
+    if ((s = count_at(c, H0, S, Sinf, Siw, mid, nullptr, &n)) != GW_OK) return s;
+    if (n < n_target) lo = mid; else hi = mid;
+    ++it;
+  }
+  const double mu = 0.5 * (lo + hi);
+  if ((s = count_at(c, H0, S, Sinf, Siw, mu, G_iw, &n)) != GW_OK) return s;
+  if ((s = read_flag(c, "find_mu")) != GW_OK) return s;
+  *mu_inout = mu;
+  if (n_out) *n_out = n;
+  if (G_tau) {
+    if ((s = gw_iw_to_tau(c, GW_FERMION, G_iw, 1, (long long)c->nk * c->n2, G_tau)) != GW_OK)
+      return s;
+  }
+  return GW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Kernel descriptors shared by the HIP kernels and the host API (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+// Index map i -> (i / (din*dmid)) * sout + ((i / din) % dmid) * smid + (i % din) * sin.
+// An affine map has din = dmid = 0x7fffffff... use aff() below.
+struct Map3 {
+  long long sout, smid, sin;
+  unsigned din, dmid;
+};
+
+static inline Map3 aff(long long s) { return Map3{0, 0, s, 0x7fffffffu, 1u}; }
+static inline Map3 two(unsigned din, long long sin, long long sout) {
+  return Map3{sout, 0, sin, din, 1u};
+}
+static inline Map3 three(unsigned din, long long sin, unsigned dmid, long long smid, long long sout) {
+  return Map3{sout, smid, sin, din, dmid};
+}
+
+// C[b](m, n) = alpha * sum_k op(A)[b](m, k) * op(B)[b](k, n) + beta * C[b](m, n)
+// with A[b](m, k) = A[ba(b) + tab[b % tmod] * tsA + am(m) + ak(k)] (conjugated if conjA),
+// and likewise for B and C.  Offsets count complex elements.
+struct GemmDesc {
+  const double2* A;
+  const double2* B;
+  double2* C;
+  int M, N, K, batch;
+  Map3 am, ak, bk, bn, cm, cn;
+  Map3 ba, bb, bc;
+  const int* tab;
+  int tmod;
+  long long tsA, tsB, tsC;
+  int conjA, conjB;
+  double alpha_r, alpha_i, beta_r, beta_i;
+  int beta_zero;
+};
+
+static inline GemmDesc gemm_desc() {
+  GemmDesc d{};
+  d.ba = d.bb = d.bc = aff(0);
+  d.am = d.ak = d.bk = d.bn = d.cm = d.cn = aff(0);
+  d.tmod = 1;
+  d.alpha_r = 1.0;
+  d.beta_zero = 1;
+  d.batch = 1;
+  return d;
+}
+
+struct DysonArgs {
+  const double2* H0;
+  const double2* S;
+  const double2* Sinf;   // may be null
+  const double2* Siw;    // may be null
+  const double* wF;
+  const double2* rrow;   // electron-count row r = w Tp (nw)
+  double mu;
+  int nk, nao;
+  double2* G;            // may be null
+  double* part;          // may be null
+  int* flag;
+};
+
+hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st);
+hipError_t wdyson_launch(const double2* P0, double2* X, double2* work, int n, long long nmat,
+                         int* flag, hipStream_t st);
+hipError_t dyson_launch(const DysonArgs& a, int nw, hipStream_t st);
+hipError_t sum_launch(const double* x, long long n, double scale, double* out, hipStream_t st);
+hipError_t trace_launch(const double2* g, const double2* S, int n, int nk, double* part,
+                        hipStream_t st);
+hipError_t mix_launch(long long n, double alpha, const double2* X, double2* Y, double* part,
+                      int nblk, hipStream_t st);
+hipError_t zero_flag_launch(int* p, hipStream_t st);

@@ -1,0 +1,633 @@
+// Device kernels of the density-fitted GW hot path for CDNA4 (gfx950).
+//
+//  * zgemm_k     batched complex fp64 GEMM on v_mfma_f64_16x16x4_f64 with
+//                per-operand index maps, used for every contraction of the
+//                polarization and self-energy chains, the tau <-> i omega
+//                transforms and the Hartree-Fock terms.
+//  * wdyson_k    (I - P0) X = P0 by LU with partial pivoting (Eq. tilde_P_omega).
+//  * dyson_k     G = [(i w + mu) S - H0 - Sigma]^{-1} by Gauss-Jordan (Eq. Dyson),
+//                with the electron-count partials of gamma = -G(beta^-).
+#include <hip/hip_runtime.h>
+
+#include "gw_kernels.h"
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ long long map3(const Map3& m, unsigned i) {
+  unsigned a = i % m.din;
+  unsigned r = i / m.din;
+  unsigned b = r % m.dmid;
+  unsigned c = r / m.dmid;
+  return (long long)c * m.sout + (long long)b * m.smid + (long long)a * m.sin;
+}
+
+// Running offset of a mapped index that advances by a fixed step.
+struct Ctr {
+  long long off;
+  unsigned a, b;
+};
+
+__device__ __forceinline__ Ctr ctr_init(const Map3& m, unsigned i) {
+  Ctr c;
+  c.a = i % m.din;
+  unsigned r = i / m.din;
+  c.b = r % m.dmid;
+  unsigned o = r / m.dmid;
+  c.off = (long long)o * m.sout + (long long)c.b * m.smid + (long long)c.a * m.sin;
+  return c;
+}
+
+__device__ __forceinline__ void ctr_step(const Map3& m, Ctr& c, unsigned st) {
+  c.a += st;
+  c.off += (long long)st * m.sin;
+  while (c.a >= m.din) {
+    c.a -= m.din;
+    c.off -= (long long)m.din * m.sin;
+    c.off += m.smid;
+    if (++c.b >= m.dmid) {
+      c.b = 0;
+      c.off -= (long long)m.dmid * m.smid;
+      c.off += m.sout;
+    }
+  }
+}
+
+__device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, int tmod, long long ts,
+                                               unsigned b) {
+  long long o = map3(m, b);
+  if (ts != 0) o += (long long)tab[b % (unsigned)tmod] * ts;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]
+// Waves: WM x WN tile the output, WK split the K loop (reduced through LDS).
+// Each wave owns BM x BN blocks of 16 x 16 complex outputs.  The fragments of
+// A and B are loaded straight from global memory (one complex per lane per
+// block per K-step of 4) and double-buffered in registers: an fp64 MFMA runs
+// long enough on CDNA4 that operand traffic is small next to it.
+template <int WM, int WN, int WK, int BM, int BN>
+__global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
+  constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave % WM, wn = (wave / WM) % WN, wk = wave / (WM * WN);
+  const int tiles_m = (d.M + TM - 1) / TM;
+  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const unsigned bt = blockIdx.y;
+
+  const double2* A = d.A + batch_off(d.ba, d.tab, d.tmod, d.tsA, bt);
+  const double2* B = d.B + batch_off(d.bb, d.tab, d.tmod, d.tsB, bt);
+  double2* C = d.C + batch_off(d.bc, d.tab, d.tmod, d.tsC, bt);
+
+  const int m0 = tm * TM + wm * BM * 16;
+  const int n0 = tn * TN + wn * BN * 16;
+  const int r16 = lane & 15;
+  const int kl = lane >> 4;
+
+  long long aoff[BM], boff[BN];
+  bool av[BM], bv[BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i) {
+    const int m = m0 + i * 16 + r16;
+    av[i] = m < d.M;
+    aoff[i] = av[i] ? map3(d.am, m) : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < BN; ++j) {
+    const int n = n0 + j * 16 + r16;
+    bv[j] = n < d.N;
+    boff[j] = bv[j] ? map3(d.bn, n) : 0;
+  }
+
+  d4 accR[BM][BN], accI[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  const unsigned kstep = 4u * WK;
+  unsigned k = 4u * wk + kl;
+  Ctr ca = ctr_init(d.ak, k), cb = ctr_init(d.bk, k);
+  const double sa = d.conjA ? -1.0 : 1.0;
+  const double sb = d.conjB ? -1.0 : 1.0;
+
+  double2 a_cur[BM], b_cur[BN];
+  {
+    const bool kv = k < (unsigned)d.K;
+#pragma unroll
+    for (int i = 0; i < BM; ++i) a_cur[i] = (av[i] && kv) ? A[aoff[i] + ca.off] : double2{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < BN; ++j) b_cur[j] = (bv[j] && kv) ? B[boff[j] + cb.off] : double2{0.0, 0.0};
+  }
+  for (unsigned k0 = 4u * wk; k0 < (unsigned)d.K; k0 += kstep) {
+    // prefetch the next K-step
+    ctr_step(d.ak, ca, kstep);
+    ctr_step(d.bk, cb, kstep);
+    k += kstep;
+    double2 a_nxt[BM], b_nxt[BN];
+    const bool kv = k < (unsigned)d.K;
+#pragma unroll
+    for (int i = 0; i < BM; ++i) a_nxt[i] = (av[i] && kv) ? A[aoff[i] + ca.off] : double2{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < BN; ++j) b_nxt[j] = (bv[j] && kv) ? B[boff[j] + cb.off] : double2{0.0, 0.0};
+
+    double ar[BM], ai[BM], nai[BM], br[BN], bi[BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+      ar[i] = a_cur[i].x;
+      ai[i] = sa * a_cur[i].y;
+      nai[i] = -ai[i];
+    }
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      br[j] = b_cur[j].x;
+      bi[j] = sb * b_cur[j].y;
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
+        accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], accR[i][j], 0, 0, 0);
+        accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < BM; ++i) a_cur[i] = a_nxt[i];
+#pragma unroll
+    for (int j = 0; j < BN; ++j) b_cur[j] = b_nxt[j];
+  }
+
+  if constexpr (WK > 1) {
+    // deterministic split-K reduction: waves wk > 0 park their sums in LDS,
+    // wave wk = 0 adds them in wk order.
+    __shared__ double red[(WK > 1 ? WK - 1 : 1) * WM * WN * BM * BN * 8 * 64];
+    const int slot = (wm + WM * wn) * BM * BN * 8;
+    if (wk > 0) {
+      double* p = red + ((size_t)(wk - 1) * WM * WN * BM * BN * 8) * 64;
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            p[(slot + ((i * BN + j) * 8 + r)) * 64 + lane] = accR[i][j][r];
+            p[(slot + ((i * BN + j) * 8 + 4 + r)) * 64 + lane] = accI[i][j][r];
+          }
+    }
+    __syncthreads();
+    if (wk > 0) return;
+    for (int w = 1; w < WK; ++w) {
+      const double* p = red + ((size_t)(w - 1) * WM * WN * BM * BN * 8) * 64;
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            accR[i][j][r] += p[(slot + ((i * BN + j) * 8 + r)) * 64 + lane];
+            accI[i][j][r] += p[(slot + ((i * BN + j) * 8 + 4 + r)) * 64 + lane];
+          }
+    }
+  }
+
+  // epilogue: for v_mfma_f64_16x16x4_f64 lane l holds column l%16 and rows
+  // l/16 + 4r (r = 0..3) of each 16 x 16 block
+#pragma unroll
+  for (int j = 0; j < BN; ++j) {
+    const int n = n0 + j * 16 + r16;
+    if (n >= d.N) continue;
+    const long long con = map3(d.cn, n);
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + i * 16 + kl + 4 * r;
+        if (m >= d.M) continue;
+        const long long o = map3(d.cm, m) + con;
+        const double xr = accR[i][j][r], xi = accI[i][j][r];
+        double2 v;
+        v.x = d.alpha_r * xr - d.alpha_i * xi;
+        v.y = d.alpha_r * xi + d.alpha_i * xr;
+        if (!d.beta_zero) {
+          const double2 c = C[o];
+          v.x += d.beta_r * c.x - d.beta_i * c.y;
+          v.y += d.beta_r * c.y + d.beta_i * c.x;
+        }
+        C[o] = v;
+      }
+  }
+}
+
+template <int WM, int WN, int WK, int BM, int BN>
+static hipError_t launch_cfg(const GemmDesc& d, hipStream_t st) {
+  constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
+  const long long tiles = (long long)((d.M + TM - 1) / TM) * ((d.N + TN - 1) / TN);
+  if (tiles > 0x7fffffffLL || d.batch > 65535) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)tiles, (unsigned)d.batch, 1);
+  zgemm_k<WM, WN, WK, BM, BN><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+  if (d.K <= 0) return hipErrorInvalidValue;
+  if (d.M <= 32 && d.N <= 32) return launch_cfg<1, 1, 4, 2, 2>(d, st);
+  return launch_cfg<2, 2, 1, 2, 2>(d, st);
+}
+
+// ---------------------------------------------------------------------------
+// (I - P0) X = P0, one workgroup per matrix.  The LU factors of I - P0 live
+// in `work`; the right-hand side is X itself.  Row pivoting by the largest
+// |re| + |im| (smallest row index on ties).
+__global__ void __launch_bounds__(1024) wdyson_k(const double2* __restrict__ P0, double2* X,
+                                                 double2* work, int n, int* flag) {
+  const size_t nn = (size_t)n * n;
+  const double2* P = P0 + blockIdx.x * nn;
+  double2* Amat = work + blockIdx.x * nn;
+  double2* Bmat = X + blockIdx.x * nn;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  __shared__ int piv_s;
+  __shared__ double2 pinv_s;
+
+  for (size_t e = tid; e < nn; e += nt) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    const double2 p = P[e];
+    Amat[e] = double2{(r == c ? 1.0 : 0.0) - p.x, -p.y};
+    Bmat[e] = p;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double best = -1.0;
+    int bi = j;
+    for (int r = j + tid; r < n; r += nt) {
+      const double2 a = Amat[(size_t)r * n + j];
+      const double v = fabs(a.x) + fabs(a.y);
+      if (v > best) { best = v; bi = r; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double o = sv[tid + s];
+        const int oi = si[tid + s];
+        if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) { sv[tid] = o; si[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      piv_s = si[0];
+      if (!(sv[0] > 0.0)) atomicOr(flag, 1);
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != j) {
+      for (int c = tid; c < n; c += nt) {
+        double2 t = Amat[(size_t)j * n + c];
+        Amat[(size_t)j * n + c] = Amat[(size_t)p * n + c];
+        Amat[(size_t)p * n + c] = t;
+        t = Bmat[(size_t)j * n + c];
+        Bmat[(size_t)j * n + c] = Bmat[(size_t)p * n + c];
+        Bmat[(size_t)p * n + c] = t;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double2 a = Amat[(size_t)j * n + j];
+      const double den = a.x * a.x + a.y * a.y;
+      pinv_s = den > 0.0 ? double2{a.x / den, -a.y / den} : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    const double2 pi = pinv_s;
+    for (int r = j + 1 + tid; r < n; r += nt) {
+      const double2 a = Amat[(size_t)r * n + j];
+      Amat[(size_t)r * n + j] = double2{a.x * pi.x - a.y * pi.y, a.x * pi.y + a.y * pi.x};
+    }
+    __syncthreads();
+    const int rows = n - j - 1;
+    const size_t cntA = (size_t)rows * (n - j - 1);
+    for (size_t e = tid; e < cntA; e += nt) {
+      const int r = j + 1 + (int)(e / (n - j - 1));
+      const int c = j + 1 + (int)(e % (n - j - 1));
+      const double2 l = Amat[(size_t)r * n + j];
+      const double2 u = Amat[(size_t)j * n + c];
+      double2 a = Amat[(size_t)r * n + c];
+      a.x -= l.x * u.x - l.y * u.y;
+      a.y -= l.x * u.y + l.y * u.x;
+      Amat[(size_t)r * n + c] = a;
+    }
+    const size_t cntB = (size_t)rows * n;
+    for (size_t e = tid; e < cntB; e += nt) {
+      const int r = j + 1 + (int)(e / n);
+      const int c = (int)(e % n);
+      const double2 l = Amat[(size_t)r * n + j];
+      const double2 u = Bmat[(size_t)j * n + c];
+      double2 b = Bmat[(size_t)r * n + c];
+      b.x -= l.x * u.x - l.y * u.y;
+      b.y -= l.x * u.y + l.y * u.x;
+      Bmat[(size_t)r * n + c] = b;
+    }
+    __syncthreads();
+  }
+  // back substitution with the upper factor
+  for (int j = n - 1; j >= 0; --j) {
+    if (tid == 0) {
+      const double2 a = Amat[(size_t)j * n + j];
+      const double den = a.x * a.x + a.y * a.y;
+      pinv_s = den > 0.0 ? double2{a.x / den, -a.y / den} : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    const double2 pi = pinv_s;
+    for (int c = tid; c < n; c += nt) {
+      const double2 b = Bmat[(size_t)j * n + c];
+      Bmat[(size_t)j * n + c] = double2{b.x * pi.x - b.y * pi.y, b.x * pi.y + b.y * pi.x};
+    }
+    __syncthreads();
+    const size_t cnt = (size_t)j * n;
+    for (size_t e = tid; e < cnt; e += nt) {
+      const int r = (int)(e / n), c = (int)(e % n);
+      const double2 u = Amat[(size_t)r * n + j];
+      const double2 x = Bmat[(size_t)j * n + c];
+      double2 b = Bmat[(size_t)r * n + c];
+      b.x -= u.x * x.x - u.y * x.y;
+      b.y -= u.x * x.y + u.y * x.x;
+      Bmat[(size_t)r * n + c] = b;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t wdyson_launch(const double2* P0, double2* X, double2* work, int n, long long nmat,
+                         int* flag, hipStream_t st) {
+  if (nmat <= 0) return hipSuccess;
+  if (nmat > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  wdyson_k<<<(unsigned)nmat, 1024, 0, st>>>(P0, X, work, n, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup per (n, k): in-place Gauss-Jordan inversion with row pivoting
+// of M = (i w_n + mu) S - H0 - Sig_inf - Sig_iw in LDS.  When G is non-null the
+// inverse is written out; when part is non-null, part[n*nk+k] receives
+// Re(r_n tr[G S]) for the electron count.
+__global__ void __launch_bounds__(256) dyson_k(DysonArgs a) {
+  extern __shared__ double2 sm[];
+  const int n = a.nao;
+  const int k = blockIdx.x % a.nk, iw = blockIdx.x / a.nk;
+  double2* M = sm;                          // n x n
+  double2* fcol = sm + n * n;               // n
+  int* perm = (int*)(fcol + n);             // n
+  __shared__ double pv[256];
+  __shared__ int pi_[256];
+  __shared__ double2 pinv_s;
+  __shared__ int piv_s;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const size_t nn = (size_t)n * n;
+  const double w = a.wF[iw];
+  for (int e = tid; e < (int)nn; e += nt) {
+    const int r = e / n, c = e % n;
+    const double2 s = a.S[k * nn + e];
+    const double2 h = a.H0[k * nn + e];
+    double2 v;
+    v.x = a.mu * s.x - w * s.y - h.x;
+    v.y = a.mu * s.y + w * s.x - h.y;
+    if (a.Sinf) { v.x -= a.Sinf[k * nn + e].x; v.y -= a.Sinf[k * nn + e].y; }
+    if (a.Siw) {
+      const double2 q = a.Siw[((size_t)iw * a.nk + k) * nn + e];
+      v.x -= q.x;
+      v.y -= q.y;
+    }
+    M[e] = v;
+    (void)r; (void)c;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double best = -1.0;
+    int bi = j;
+    for (int r = j + tid; r < n; r += nt) {
+      const double2 x = M[r * n + j];
+      const double v = fabs(x.x) + fabs(x.y);
+      if (v > best) { best = v; bi = r; }
+    }
+    pv[tid] = best;
+    pi_[tid] = bi;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        if (pv[tid + s] > pv[tid] || (pv[tid + s] == pv[tid] && pi_[tid + s] < pi_[tid])) {
+          pv[tid] = pv[tid + s];
+          pi_[tid] = pi_[tid + s];
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      piv_s = pi_[0];
+      perm[j] = pi_[0];
+      if (!(pv[0] > 0.0)) atomicOr(a.flag, 1);
+    }
+    __syncthreads();
+    const int p = piv_s;
+    if (p != j)
+      for (int c = tid; c < n; c += nt) {
+        const double2 t = M[j * n + c];
+        M[j * n + c] = M[p * n + c];
+        M[p * n + c] = t;
+      }
+    __syncthreads();
+    if (tid == 0) {
+      const double2 x = M[j * n + j];
+      const double den = x.x * x.x + x.y * x.y;
+      pinv_s = den > 0.0 ? double2{x.x / den, -x.y / den} : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    const double2 q = pinv_s;
+    for (int c = tid; c < n; c += nt) {
+      const double2 x = (c == j) ? double2{1.0, 0.0} : M[j * n + c];
+      M[j * n + c] = double2{x.x * q.x - x.y * q.y, x.x * q.y + x.y * q.x};
+    }
+    for (int r = tid; r < n; r += nt) fcol[r] = M[r * n + j];
+    __syncthreads();
+    for (int e = tid; e < (int)nn; e += nt) {
+      const int r = e / n, c = e % n;
+      if (r == j) continue;
+      const double2 f = fcol[r];
+      const double2 u = M[j * n + c];
+      double2 x = (c == j) ? double2{0.0, 0.0} : M[e];
+      x.x -= f.x * u.x - f.y * u.y;
+      x.y -= f.x * u.y + f.y * u.x;
+      M[e] = x;
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges of the inverse
+  for (int j = n - 1; j >= 0; --j) {
+    const int p = perm[j];
+    if (p != j)
+      for (int r = tid; r < n; r += nt) {
+        const double2 t = M[r * n + j];
+        M[r * n + j] = M[r * n + p];
+        M[r * n + p] = t;
+      }
+    __syncthreads();
+  }
+  if (a.G) {
+    double2* g = a.G + ((size_t)iw * a.nk + k) * nn;
+    for (int e = tid; e < (int)nn; e += nt) g[e] = M[e];
+  }
+  if (a.part) {
+    // tr[G S] = sum_{ij} G_ij S_ji
+    double tr_r = 0.0, tr_i = 0.0;
+    for (int e = tid; e < (int)nn; e += nt) {
+      const int r = e / n, c = e % n;
+      const double2 g = M[e];
+      const double2 s = a.S[k * nn + (size_t)c * n + r];
+      tr_r += g.x * s.x - g.y * s.y;
+      tr_i += g.x * s.y + g.y * s.x;
+    }
+    pv[tid] = tr_r;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) pv[tid] += pv[tid + s];
+      __syncthreads();
+    }
+    const double sr = pv[0];
+    __syncthreads();
+    pv[tid] = tr_i;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) pv[tid] += pv[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double2 rr = a.rrow[iw];
+      a.part[(size_t)iw * a.nk + k] = rr.x * sr - rr.y * pv[0];
+    }
+  }
+}
+
+hipError_t dyson_launch(const DysonArgs& a, int nw, hipStream_t st) {
+  if (nw <= 0 || a.nk <= 0) return hipSuccess;
+  const size_t shm = (size_t)a.nao * a.nao * sizeof(double2) + (size_t)a.nao * sizeof(double2) +
+                     (size_t)a.nao * sizeof(int);
+  dyson_k<<<(unsigned)(nw * a.nk), 256, shm, st>>>(a);
+  return hipGetLastError();
+}
+
+// Sum of x[0..n) in a fixed order (one workgroup), out[0] = scale * sum.
+__global__ void __launch_bounds__(256) sum_k(const double* x, long long n, double scale,
+                                              double* out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) acc += x[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = scale * s[0];
+}
+
+hipError_t sum_launch(const double* x, long long n, double scale, double* out, hipStream_t st) {
+  sum_k<<<1, 256, 0, st>>>(x, n, scale, out);
+  return hipGetLastError();
+}
+
+// part[k] = Re tr[gamma^k S^k]
+__global__ void __launch_bounds__(64) trace_k(const double2* g, const double2* S, int n,
+                                             double* part) {
+  const int k = blockIdx.x;
+  const size_t nn = (size_t)n * n;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < (int)nn; e += 64) {
+    const int r = e / n, c = e % n;
+    const double2 x = g[k * nn + e];
+    const double2 s = S[k * nn + (size_t)c * n + r];
+    acc += x.x * s.x - x.y * s.y;
+  }
+  __shared__ double sh[64];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[k] = sh[0];
+}
+
+hipError_t trace_launch(const double2* g, const double2* S, int n, int nk, double* part,
+                        hipStream_t st) {
+  trace_k<<<nk, 64, 0, st>>>(g, S, n, part);
+  return hipGetLastError();
+}
+
+// Y = (1 - alpha) Y + alpha X (X may be null); per-block max |X - Y_old| into part.
+__global__ void __launch_bounds__(256) mix_k(long long n, double alpha, const double2* X, double2* Y,
+                                              double* part) {
+  __shared__ double s[256];
+  double mx = 0.0;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
+    const double2 x = X ? X[i] : double2{0.0, 0.0};
+    double2 y;
+    if (alpha == 1.0 && !part) {
+      y = double2{0.0, 0.0};
+    } else {
+      y = Y[i];
+      const double dx = x.x - y.x, dy = x.y - y.y;
+      mx = fmax(mx, sqrt(dx * dx + dy * dy));
+    }
+    Y[i] = double2{y.x + alpha * (x.x - y.x), y.y + alpha * (x.y - y.y)};
+  }
+  if (!part) return;
+  s[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(256) max_k(const double* x, int n, double* out) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, x[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+hipError_t mix_launch(long long n, double alpha, const double2* X, double2* Y, double* part,
+                      int nblk, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  mix_k<<<nblk, 256, 0, st>>>(n, alpha, X, Y, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !part) return e;
+  max_k<<<1, 256, 0, st>>>(part, nblk, part + nblk);
+  return hipGetLastError();
+}
+
+__global__ void zero_int_k(int* p) { *p = 0; }
+
+hipError_t zero_flag_launch(int* p, hipStream_t st) {
+  zero_int_k<<<1, 1, 0, st>>>(p);
+  return hipGetLastError();
+}

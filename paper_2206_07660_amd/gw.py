@@ -1,0 +1,295 @@
+"""Python binding of libgw.so (the C ABI declared in include/gw.h).
+
+Argument marshalling only: every step of the GW path runs in the library's
+HIP kernels.  PyTorch supplies device memory and the stream.  The functions
+keep the C names; array arguments are torch complex128 tensors on the GPU in
+the layouts of include/gw.h.  If the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgw.so")
+
+GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPACE, GW_ERR_STATE = range(7)
+GW_FERMION, GW_BOSON = 0, 1
+GW_PREC_FP64 = 0
+GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF = range(4)
+
+EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_workspace_bytes",
+           "gw_set_workspace", "gw_polarization", "gw_tau_to_iw", "gw_iw_to_tau",
+           "gw_screened_W", "gw_self_energy", "gw_density", "gw_hf", "gw_dyson_G",
+           "gw_find_mu", "gw_mix", "gw_grids_host", "gw_synchronize", "gw_status_string", "gw_last_error"]
+
+
+class GwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("mesh", ctypes.c_int * 3), ("nao", ctypes.c_int), ("naux", ctypes.c_int),
+                ("ntau", ctypes.c_int), ("nw_f", ctypes.c_int), ("nw_b", ctypes.c_int),
+                ("ns", ctypes.c_int), ("precision", ctypes.c_int), ("beta", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgw.so from the package directory (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2206_07660_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, LL, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_size_t
+    sig = {
+        "gw_create": ([ctypes.POINTER(Dims), P, ctypes.POINTER(P)], I),
+        "gw_destroy": ([P], I),
+        "gw_build_grids": ([P, P, P], I),
+        "gw_get_grids": ([P, P, P, P, P, P, P, P, P], I),
+        "gw_workspace_bytes": ([P, I, I], SZ),
+        "gw_set_workspace": ([P, P, SZ, I], I),
+        "gw_polarization": ([P, P, P, I, I, P], I),
+        "gw_tau_to_iw": ([P, I, P, LL, LL, P], I),
+        "gw_iw_to_tau": ([P, I, P, LL, LL, P], I),
+        "gw_screened_W": ([P, P, I, P], I),
+        "gw_self_energy": ([P, P, P, P, I, I, P], I),
+        "gw_density": ([P, P, P, P, P], I),
+        "gw_hf": ([P, P, P, P, P], I),
+        "gw_dyson_G": ([P, P, P, P, P, D, P], I),
+        "gw_find_mu": ([P, P, P, P, P, D, D, P, P, P, P], I),
+        "gw_synchronize": ([P], I),
+        "gw_mix": ([P, LL, D, P, P, P], I),
+        "gw_grids_host": ([D, I, P, P, P, P, P, P, P, P, P, P], I),
+        "gw_status_string": ([I], ctypes.c_char_p),
+        "gw_last_error": ([P], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(t, name, shape=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def gw_grids_host(beta, ntau, nF=None, nB=None):
+    """Host-only grid tables (no GPU needed); same content as Context.get_grids()."""
+    L = load()
+    nt, nf, nb = int(ntau), int(ntau), int(ntau) + 1
+    out = dict(tau=np.zeros(nt), nF=np.zeros(nf, np.int64), nB=np.zeros(nb, np.int64),
+               TF=np.zeros((nf, nt), np.complex128), TFp=np.zeros((nt, nf), np.complex128),
+               TB=np.zeros((nb, nt), np.complex128), TBp=np.zeros((nt, nb), np.complex128),
+               w=np.zeros(nt))
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    nfa = None if nF is None else np.ascontiguousarray(nF, np.int64)
+    nba = None if nB is None else np.ascontiguousarray(nB, np.int64)
+    st = L.gw_grids_host(float(beta), nt, p(nfa) if nfa is not None else None,
+                         p(nba) if nba is not None else None, p(out["tau"]), p(out["nF"]),
+                         p(out["nB"]), p(out["TF"]), p(out["TFp"]), p(out["TB"]), p(out["TBp"]),
+                         p(out["w"]))
+    if st != GW_OK:
+        raise GwError(st, "gw_grids_host: " + L.gw_status_string(st).decode())
+    return out
+
+
+class Context:
+    """One library context: dimensions, grids, stream and workspace."""
+
+    def __init__(self, mesh, nao, naux, ntau, beta, ns=2, nF=None, nB=None, tau_chunk=None,
+                 max_nq=None, stream=None, workspace_gb=None):
+        import torch
+        L = load()
+        self.mesh = tuple(int(m) for m in mesh)
+        self.nk = int(np.prod(self.mesh))
+        self.nao, self.naux, self.ntau, self.beta, self.ns = int(nao), int(naux), int(ntau), float(beta), int(ns)
+        self.nw_f, self.nw_b = self.ntau, self.ntau + 1
+        d = Dims((ctypes.c_int * 3)(*self.mesh), self.nao, self.naux, self.ntau, self.nw_f,
+                 self.nw_b, self.ns, GW_PREC_FP64, self.beta)
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        st = L.gw_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != GW_OK:
+            raise GwError(st, "gw_create failed: " + L.gw_status_string(st).decode())
+        self.h = h
+        nf = None if nF is None else (ctypes.c_longlong * self.nw_f)(*[int(x) for x in nF])
+        nb = None if nB is None else (ctypes.c_longlong * self.nw_b)(*[int(x) for x in nB])
+        self._check(L.gw_build_grids(self.h, nf, nb), "gw_build_grids")
+        # workspace: largest tau chunk that fits the budget (default 40% of free memory)
+        free, _ = torch.cuda.mem_get_info()
+        budget = int((workspace_gb * 2 ** 30) if workspace_gb else 0.4 * free)
+        self.max_nq = self.nk if max_nq is None else int(max_nq)
+        if tau_chunk is None:
+            tau_chunk = self.ntau
+            while tau_chunk > 1 and L.gw_workspace_bytes(self.h, GW_OP_POLARIZATION, tau_chunk) > budget:
+                tau_chunk = (tau_chunk + 1) // 2
+        self.tau_chunk = int(tau_chunk)
+        need = max(L.gw_workspace_bytes(self.h, GW_OP_POLARIZATION, self.tau_chunk),
+                   L.gw_workspace_bytes(self.h, GW_OP_SCREENED_W, self.max_nq),
+                   L.gw_workspace_bytes(self.h, GW_OP_HF, 1))
+        self.workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(L.gw_set_workspace(self.h, ctypes.c_void_p(aligned), need, self.tau_chunk),
+                    "gw_set_workspace")
+        self.grids = self.get_grids()
+
+    def _check(self, st, what):
+        if st != GW_OK:
+            L = load()
+            raise GwError(st, f"{what}: {L.gw_status_string(st).decode()}: "
+                              f"{L.gw_last_error(self.h).decode()}")
+
+    def get_grids(self):
+        L = load()
+        nt, nf, nb = self.ntau, self.nw_f, self.nw_b
+        out = dict(tau=np.zeros(nt), nF=np.zeros(nf, np.int64), nB=np.zeros(nb, np.int64),
+                   TF=np.zeros((nf, nt), np.complex128), TFp=np.zeros((nt, nf), np.complex128),
+                   TB=np.zeros((nb, nt), np.complex128), TBp=np.zeros((nt, nb), np.complex128),
+                   w=np.zeros(nt))
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._check(L.gw_get_grids(self.h, p(out["tau"]), p(out["nF"]), p(out["nB"]), p(out["TF"]),
+                                   p(out["TFp"]), p(out["TB"]), p(out["TBp"]), p(out["w"])),
+                    "gw_get_grids")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            load().gw_destroy(self.h)
+            self.h = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes
+    def g_shape(self):
+        return (self.ntau, self.nk, self.nao, self.nao)
+
+    def giw_shape(self):
+        return (self.nw_f, self.nk, self.nao, self.nao)
+
+    def v_shape(self):
+        return (self.nk, self.nk, self.naux, self.nao, self.nao)
+
+    def k_shape(self):
+        return (self.nk, self.nao, self.nao)
+
+
+# --------------------------------------------------------------- the calls ---
+def gw_polarization(ctx, V, G_tau, q0, nq, P0_tau):
+    ctx._check(load().gw_polarization(
+        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()), int(q0), int(nq),
+        _ptr(P0_tau, "P0_tau", (nq, ctx.ntau, ctx.naux, ctx.naux))), "gw_polarization")
+
+
+def _transform(fn, ctx, stat, Xin, Xout, batch, fwd):
+    nw = ctx.nw_f if stat == GW_FERMION else ctx.nw_b
+    nin, nout = (ctx.ntau, nw) if fwd else (nw, ctx.ntau)
+    if Xin.numel() % (batch * nin):
+        raise ValueError("input size is not a multiple of batch * rows")
+    R = Xin.numel() // (batch * nin)
+    if Xout.numel() != batch * nout * R:
+        raise ValueError("output size does not match")
+    ctx._check(fn(ctx.h, int(stat), _ptr(Xin, "X_in"), int(batch), int(R), _ptr(Xout, "X_out")),
+               fn.__name__)
+
+
+def gw_tau_to_iw(ctx, stat, X_tau, X_iw, batch=1):
+    """X_iw[b][n][r] = sum_i T[n][i] X_tau[b][i][r]  (tensors [batch][ntau][...])."""
+    _transform(load().gw_tau_to_iw, ctx, stat, X_tau, X_iw, batch, True)
+
+
+def gw_iw_to_tau(ctx, stat, X_iw, X_tau, batch=1):
+    """X_tau[b][i][r] = sum_n Tp[i][n] X_iw[b][n][r]."""
+    _transform(load().gw_iw_to_tau, ctx, stat, X_iw, X_tau, batch, False)
+
+
+def gw_mix(ctx, alpha, X_new, Y, want_diff=False):
+    """Y <- (1 - alpha) Y + alpha X_new; returns max |X_new - Y_old| when asked."""
+    if X_new is not None and X_new.numel() != Y.numel():
+        raise ValueError("gw_mix sizes differ")
+    d = ctypes.c_double()
+    ctx._check(load().gw_mix(ctx.h, int(Y.numel()), float(alpha),
+                             _ptr(X_new, "X_new") if X_new is not None else None, _ptr(Y, "Y"),
+                             ctypes.byref(d) if want_diff else None), "gw_mix")
+    return d.value if want_diff else None
+
+
+def gw_screened_W(ctx, P0_iw, Pt_iw):
+    nq = int(P0_iw.shape[0])
+    shp = (nq, ctx.nw_b, ctx.naux, ctx.naux)
+    ctx._check(load().gw_screened_W(ctx.h, _ptr(P0_iw, "P0_iw", shp), nq, _ptr(Pt_iw, "Pt_iw", shp)),
+               "gw_screened_W")
+
+
+def gw_self_energy(ctx, V, G_tau, Pt_tau, q0, nq, Sig_tau):
+    ctx._check(load().gw_self_energy(
+        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        _ptr(Pt_tau, "Pt_tau", (nq, ctx.ntau, ctx.naux, ctx.naux)), int(q0), int(nq),
+        _ptr(Sig_tau, "Sig_tau", ctx.g_shape())), "gw_self_energy")
+
+
+def gw_density(ctx, G_tau, S, gamma, want_count=True):
+    n = ctypes.c_double()
+    ctx._check(load().gw_density(ctx.h, _ptr(G_tau, "G_tau", ctx.g_shape()),
+                                 _ptr(S, "S", ctx.k_shape()), _ptr(gamma, "gamma", ctx.k_shape()),
+                                 ctypes.byref(n) if want_count else None), "gw_density")
+    return n.value if want_count else None
+
+
+def gw_hf(ctx, V, G_tau, gamma, Sig_inf):
+    ctx._check(load().gw_hf(ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+                            _ptr(gamma, "gamma", ctx.k_shape()) if gamma is not None else None,
+                            _ptr(Sig_inf, "Sig_inf", ctx.k_shape())), "gw_hf")
+
+
+def gw_dyson_G(ctx, H0, S, Sig_inf, Sig_iw, mu, G_iw):
+    ctx._check(load().gw_dyson_G(
+        ctx.h, _ptr(H0, "H0", ctx.k_shape()), _ptr(S, "S", ctx.k_shape()),
+        _ptr(Sig_inf, "Sig_inf", ctx.k_shape()) if Sig_inf is not None else None,
+        _ptr(Sig_iw, "Sig_iw", ctx.giw_shape()) if Sig_iw is not None else None,
+        float(mu), _ptr(G_iw, "G_iw", ctx.giw_shape())), "gw_dyson_G")
+
+
+def gw_find_mu(ctx, H0, S, Sig_inf, Sig_iw, n_target, mu0=0.0, tol=1e-13, G_iw=None, G_tau=None):
+    mu = ctypes.c_double(mu0)
+    n = ctypes.c_double()
+    ctx._check(load().gw_find_mu(
+        ctx.h, _ptr(H0, "H0", ctx.k_shape()), _ptr(S, "S", ctx.k_shape()),
+        _ptr(Sig_inf, "Sig_inf", ctx.k_shape()) if Sig_inf is not None else None,
+        _ptr(Sig_iw, "Sig_iw", ctx.giw_shape()) if Sig_iw is not None else None,
+        float(n_target), float(tol), ctypes.byref(mu),
+        _ptr(G_iw, "G_iw", ctx.giw_shape()) if G_iw is not None else None,
+        _ptr(G_tau, "G_tau", ctx.g_shape()) if G_tau is not None else None,
+        ctypes.byref(n)), "gw_find_mu")
+    return mu.value, n.value
+
+
+def gw_synchronize(ctx):
+    ctx._check(load().gw_synchronize(ctx.h), "gw_synchronize")

@@ -1,0 +1,79 @@
+"""Host-side checks of libgw.so: it loads, exports every symbol the header
+declares, rejects bad arguments before touching a GPU, and its host-built
+grids agree with the oracle's independent construction."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2206_07660_amd import gw
+from oracle import grids as og
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gw.load()
+    hdr = open(os.path.join(ROOT, "include", "gw.h")).read()
+    names = set(re.findall(r"\b(gw_[a-z_A-Z]+)\s*\(", hdr))
+    assert len(names) >= 18
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(gw.EXPORTS) <= names
+
+
+def test_status_strings():
+    L = gw.load()
+    for s in range(7):
+        assert L.gw_status_string(s)
+    assert L.gw_status_string(2) == b"HIP runtime error"
+
+
+@pytest.mark.parametrize("field,value", [("nao", 0), ("nao", 61), ("ntau", 7), ("ns", 3),
+                                         ("nw_f", 5), ("nw_b", 10), ("beta", -1.0),
+                                         ("naux", 0), ("precision", 9)])
+def test_create_rejects_bad_dims_without_gpu(field, value):
+    L = gw.load()
+    d = gw.Dims((ctypes.c_int * 3)(2, 2, 2), 6, 24, 24, 24, 25, 2, 0, 50.0)
+    setattr(d, field, value)
+    h = ctypes.c_void_p()
+    assert L.gw_create(ctypes.byref(d), None, ctypes.byref(h)) == gw.GW_ERR_ARG
+    assert not h.value
+
+
+def test_create_rejects_null():
+    L = gw.load()
+    h = ctypes.c_void_p()
+    assert L.gw_create(None, None, ctypes.byref(h)) == gw.GW_ERR_ARG
+    assert L.gw_destroy(None) == gw.GW_ERR_ARG
+
+
+@pytest.mark.parametrize("beta,ntau", [(50.0, 24), (20.0, 20), (100.0, 60)])
+def test_host_grids_match_oracle(beta, ntau):
+    p = gw.gw_grids_host(beta, ntau)
+    o = og.Grids(beta, ntau)
+    assert np.array_equal(p["nF"], o.nF) and np.array_equal(p["nB"], o.nB)
+    assert np.abs(p["tau"] - o.tau).max() <= 1e-13 * beta
+    for key in ("TF", "TB", "TFp", "TBp"):
+        ref = getattr(o, key)
+        assert np.abs(p[key] - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max()), key
+    assert np.abs(p["w"] - o.w).max() < 1e-12
+
+
+def test_host_grids_reject_bad_input():
+    with pytest.raises(gw.GwError):
+        gw.gw_grids_host(-1.0, 24)
+    with pytest.raises(gw.GwError):
+        gw.gw_grids_host(10.0, 7)
+    bad = np.arange(24)[::-1].copy()     # not increasing
+    with pytest.raises(gw.GwError):
+        gw.gw_grids_host(10.0, 24, nF=bad)
+
+
+def test_host_grids_given_sets_are_used():
+    o = og.Grids(20.0, 20)
+    p = gw.gw_grids_host(20.0, 20, nF=o.nF, nB=o.nB)
+    assert np.array_equal(p["nF"], o.nF)
+    assert np.abs(p["TF"] - o.TF).max() < 1e-11
