@@ -200,6 +200,18 @@ gw_status gw_find_mu(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig
 gw_status gw_mix(gw_ctx* ctx, long long n, double alpha, const gw_z* X_new, gw_z* Y,
                  double* maxdiff);
 
+/* Measurement.  While enabled, every launch of a kernel class is bracketed
+ * by HIP events recorded on the context's stream; gw_profile_read
+ * (synchronises) returns the launch count, the summed event time in ms and
+ * the algorithmic flops of those launches (8 real flops per complex
+ * multiply-add; (32/3) n^3 per screened-interaction solve).  Enabling clears
+ * the counters.                                                             */
+enum { GW_KCLASS_OTHER = 0, GW_KCLASS_POL_CONTRACT = 1, GW_KCLASS_POL_PRODUCER = 2,
+       GW_KCLASS_SE_CONTRACT = 3, GW_KCLASS_SE_PRODUCER = 4, GW_KCLASS_SE_FINAL = 5,
+       GW_KCLASS_TRANSFORM = 6, GW_KCLASS_HF = 7, GW_KCLASS_WDYSON = 8, GW_KCLASS_DYSON = 9 };
+gw_status gw_profile_enable(gw_ctx* ctx, int on);
+gw_status gw_profile_read(gw_ctx* ctx, int kclass, long long* launches, double* ms, double* flops);
+
 /* Block until every call enqueued on the context's stream has finished. */
 gw_status gw_synchronize(gw_ctx* ctx);
 

@@ -119,7 +119,7 @@ def polarization(V, G_tau, mesh, ns, qs=None, taus=None):
             for it, t in enumerate(taus):
                 X = A @ G_tau[t, plus[q, k]]              # (Q, d, b)
                 Z = Ah @ G_tau[ntau - 1 - t, k]           # (Q', b, d)
-                out[iq, it] -= ns / nk * np.einsum("Qdb,Pbd->QP", X, Z)
+                out[iq, it] -= ns / nk * np.einsum("Qdb,Pbd->QP", X, Z, optimize=True)
     return out
 
 
@@ -163,7 +163,8 @@ def self_energy(V, G_tau, Pt_tau, mesh, qs=None, out=None):
             A = V[q, kk]                                   # (Q, b, j) = V^{k-q,k}
             for t in range(ntau):
                 B = np.tensordot(Pt_tau[iq, t], A, axes=(1, 0))      # (Q, b, j)
-                out[t, k] -= 1.0 / nk * np.einsum("Qai,ab,Qbj->ij", A.conj(), G_tau[t, kk], B)
+                out[t, k] -= 1.0 / nk * np.einsum("Qai,ab,Qbj->ij", A.conj(), G_tau[t, kk], B,
+                                                   optimize=True)
     return out
 
 

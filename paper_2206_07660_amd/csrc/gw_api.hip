@@ -28,6 +28,12 @@ struct gw_ctx {
   std::vector<gwgrid::cd> TF, TFp, TB, TBp, rrow;
   std::vector<int> plus;   // host copy of the k+q table
   bool check_bounds = false;
+  // measurement: event pairs per kernel class while profiling is on
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KC_COUNT];
+  long long launches[KC_COUNT] = {};
+  double flops[KC_COUNT] = {};
+  double ms[KC_COUNT] = {};
   double2 *dTF = nullptr, *dTFp = nullptr, *dTB = nullptr, *dTBp = nullptr;
   double2 *dw = nullptr, *drrow = nullptr;
   double* dwF = nullptr;
@@ -153,15 +159,38 @@ bool gemm_in_bounds(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC, std::s
   return true;
 }
 
+gw_status prof_begin(gw_ctx* c, int kc, hipEvent_t* e0) {
+  if (!c->prof) return GW_OK;
+  HIPCHK(c, hipEventCreate(e0));
+  HIPCHK(c, hipEventRecord(*e0, c->st));
+  (void)kc;
+  return GW_OK;
+}
+
+gw_status prof_end(gw_ctx* c, int kc, hipEvent_t e0, double flops) {
+  if (!c->prof) return GW_OK;
+  hipEvent_t e1;
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, hipEventRecord(e1, c->st));
+  c->ev[kc].push_back({e0, e1});
+  c->launches[kc] += 1;
+  c->flops[kc] += flops;
+  return GW_OK;
+}
+
 gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
   if (c->check_bounds) {
     std::string why;
     if (!gemm_in_bounds(c, g, eA, eB, eC, why))
       return fail(c, GW_ERR_ARG, "internal descriptor check: " + why);
   }
+  hipEvent_t e0 = nullptr;
+  gw_status s = prof_begin(c, g.tag, &e0);
+  if (s != GW_OK) return s;
   hipError_t e = zgemm_launch(g, c->st);
   if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("zgemm: ") + hipGetErrorString(e));
-  return GW_OK;
+  // algorithmic flops: 8 real flops per complex multiply-add
+  return prof_end(c, g.tag, e0, 8.0 * g.M * (double)g.N * g.K * g.batch);
 }
 
 gw_status read_flag(gw_ctx* c, const char* what) {
@@ -256,6 +285,11 @@ gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
 
 gw_status gw_destroy(gw_ctx* c) {
   if (!c) return GW_ERR_ARG;
+  for (int k = 0; k < KC_COUNT; ++k)
+    for (auto& p : c->ev[k]) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
   void* ptrs[] = {c->dTF, c->dTFp, c->dTB, c->dTBp, c->dw, c->drrow, c->dwF,
                   c->dplus, c->dminus, c->dflag, c->dpart};
   for (void* p : ptrs)
@@ -428,6 +462,43 @@ gw_status gw_mix(gw_ctx* c, long long n, double alpha, const gw_z* X, gw_z* Y, d
   return GW_OK;
 }
 
+gw_status gw_profile_enable(gw_ctx* c, int on) {
+  if (!c) return GW_ERR_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int k = 0; k < KC_COUNT; ++k) {
+    for (auto& p : c->ev[k]) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    c->ev[k].clear();
+    if (on) {
+      c->launches[k] = 0;
+      c->flops[k] = 0.0;
+      c->ms[k] = 0.0;
+    }
+  }
+  c->prof = on != 0;
+  return GW_OK;
+}
+
+gw_status gw_profile_read(gw_ctx* c, int kc, long long* launches, double* ms, double* flops) {
+  if (!c) return GW_ERR_ARG;
+  if (kc < 0 || kc >= KC_COUNT) return fail(c, GW_ERR_ARG, "kernel class out of range");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (auto& p : c->ev[kc]) {
+    float t = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&t, p.first, p.second));
+    c->ms[kc] += t;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  c->ev[kc].clear();
+  if (launches) *launches = c->launches[kc];
+  if (ms) *ms = c->ms[kc];
+  if (flops) *flops = c->flops[kc];
+  return GW_OK;
+}
+
 gw_status gw_synchronize(gw_ctx* c) {
   if (!c) return GW_ERR_ARG;
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -464,6 +535,7 @@ gw_status gw_polarization(gw_ctx* c, const gw_z* V, const gw_z* G, int q0, int n
       g.cm = aff(nao); g.cn = two(nao, 1, S);
       g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;   // G^{k+q}
+      g.tag = KC_POL_PRODUCER;
       gw_status s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * S});
       if (s != GW_OK) return s;
       // Zt[tl][k][Q'][d][b] = sum_c G[nt-1-t0-tl][k][c][d] conj(V[q][k][Q'][c][b])
@@ -474,6 +546,7 @@ gw_status gw_polarization(gw_ctx* c, const gw_z* V, const gw_z* G, int q0, int n
       g.bk = aff(nao); g.bn = two(nao, 1, n2); g.conjB = 1;
       g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
       g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
+      g.tag = KC_POL_PRODUCER;
       if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tc * S})) != GW_OK) return s;
       // P0[q-q0][t0+tl][Q][Q'] = -(ns/nk) sum_{k,e} X[tl][k][Q][e] Zt[tl][k][Q'][e]
       g = gemm_desc();
@@ -484,6 +557,7 @@ gw_status gw_polarization(gw_ctx* c, const gw_z* V, const gw_z* G, int q0, int n
       g.cm = aff(naux); g.cn = aff(1);
       g.ba = aff(S); g.bb = aff(S); g.bc = aff((long long)naux * naux);
       g.alpha_r = -(double)c->d.ns / nk;
+      g.tag = KC_POL_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * naux * naux})) != GW_OK) return s;
     }
   }
@@ -512,6 +586,7 @@ static gw_status transform(gw_ctx* c, int stat, const gw_z* Xin, long long batch
   g.bk = aff(R); g.bn = aff(1);
   g.cm = aff(R); g.cn = aff(1);
   g.ba = aff(0); g.bb = aff((long long)inner * R); g.bc = aff((long long)rows * R);
+  g.tag = KC_TRANSFORM;
   return run(c, g, Ext{0, (long long)rows * inner}, Ext{0, batch * inner * R}, Ext{0, batch * rows * R});
 }
 
@@ -536,8 +611,13 @@ gw_status gw_screened_W(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt) {
   if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_SCREENED_W, nq))
     return fail(c, GW_ERR_WORKSPACE, "screened_W workspace too small");
   HIPCHK(c, zero_flag_launch(c->dflag, c->st));
+  hipEvent_t e0 = nullptr;
+  gw_status s = prof_begin(c, KC_WDYSON, &e0);
+  if (s != GW_OK) return s;
   HIPCHK(c, wdyson_launch((const double2*)P0, (double2*)Pt, (double2*)c->ws, c->d.naux,
                           (long long)nq * c->d.nw_b, c->dflag, c->st));
+  const double n = c->d.naux;
+  if ((s = prof_end(c, KC_WDYSON, e0, (32.0 / 3.0) * n * n * n * nq * c->d.nw_b)) != GW_OK) return s;
   return read_flag(c, "screened_W");
 }
 
@@ -572,6 +652,7 @@ gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt
       g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
       g.cm = aff((long long)nk * n2); g.cn = aff(1);
       g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
+      g.tag = KC_SE_CONTRACT;
       gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
       if (s != GW_OK) return s;
       // L[tl][kk][Q][i][b] = sum_a conj(V[q][kk][Q][a][i]) G[t0+tl][kk][a][b]
@@ -582,6 +663,7 @@ gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt
       g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
       g.cm = aff(nao); g.cn = two(nao, 1, S);
       g.ba = aff(sv); g.bb = aff(n2); g.bc = aff(sv);
+      g.tag = KC_SE_PRODUCER;
       if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
       // Sig[t0+tl][kk+q][i][j] += -(1/nk) sum_{Q,b} L[tl][kk][Q][i][b] Vt[tl][Q][kk][b][j]
       g = gemm_desc();
@@ -594,6 +676,7 @@ gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
       g.alpha_r = -1.0 / nk;
       g.beta_zero = 0; g.beta_r = 1.0;
+      g.tag = KC_SE_FINAL;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * nk * n2})) != GW_OK) return s;
     }
   }
@@ -608,6 +691,7 @@ static gw_status gamma_of(gw_ctx* c, const gw_z* G, double2* gamma) {
   g.am = aff(0); g.ak = aff(1); g.bk = aff((long long)c->nk * c->n2); g.bn = aff(1);
   g.cm = aff(0); g.cn = aff(1);
   g.alpha_r = -1.0;
+  g.tag = KC_HF;
   return run(c, g, Ext{0, (long long)c->d.ntau}, Ext{0, (long long)c->d.ntau * c->nk * c->n2}, Ext{0, (long long)c->nk * c->n2});
 }
 
@@ -648,6 +732,7 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
   g.bk = three(nao, nao, nao, 1, n2); g.bn = aff(0);
   g.cm = aff(1); g.cn = aff(0);
   g.alpha_r = (double)c->d.ns / nk;
+  g.tag = KC_HF;
   if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)naux})) != GW_OK) return s;
   // J[k][e] = sum_Q v[Q] V[0][k][Q][e]
   g = gemm_desc();
@@ -656,6 +741,7 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
   g.am = aff(0); g.ak = aff(1);
   g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
   g.cm = aff(0); g.cn = aff(1);
+  g.tag = KC_HF;
   if ((s = run(c, g, Ext{0, (long long)naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
   for (int q = 0; q < nk; ++q) {
     const double2* Aq = Vd + (long long)q * nk * sv;
@@ -667,6 +753,7 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
     g.cm = aff(nao); g.cn = aff(1);
     g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
     g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;
+    g.tag = KC_HF;
     if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)nk * sv})) != GW_OK) return s;
     // Sinf[k][i][j] += -(1/nk) sum_{Q,b} T1[k][Q][i][b] conj(V[q][k][Q][j][b])
     g = gemm_desc();
@@ -678,6 +765,7 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
     g.ba = aff(sv); g.bb = aff(sv); g.bc = aff(n2);
     g.alpha_r = -1.0 / nk;
     g.beta_zero = 0; g.beta_r = 1.0;
+    g.tag = KC_HF;
     if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
   }
   return GW_OK;

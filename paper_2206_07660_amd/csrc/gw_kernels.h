@@ -20,6 +20,11 @@ static inline Map3 three(unsigned din, long long sin, unsigned dmid, long long s
 // C[b](m, n) = alpha * sum_k op(A)[b](m, k) * op(B)[b](k, n) + beta * C[b](m, n)
 // with A[b](m, k) = A[ba(b) + tab[b % tmod] * tsA + am(m) + ak(k)] (conjugated if conjA),
 // and likewise for B and C.  Offsets count complex elements.
+// Kernel classes (profiling roles); values match GW_KCLASS_* of gw.h.
+enum { KC_OTHER = 0, KC_POL_CONTRACT = 1, KC_POL_PRODUCER = 2, KC_SE_CONTRACT = 3,
+       KC_SE_PRODUCER = 4, KC_SE_FINAL = 5, KC_TRANSFORM = 6, KC_HF = 7, KC_WDYSON = 8,
+       KC_DYSON = 9, KC_COUNT = 10 };
+
 struct GemmDesc {
   const double2* A;
   const double2* B;
@@ -33,6 +38,7 @@ struct GemmDesc {
   int conjA, conjB;
   double alpha_r, alpha_i, beta_r, beta_i;
   int beta_zero;
+  int tag;   // KC_*
 };
 
 static inline GemmDesc gemm_desc() {

@@ -66,7 +66,8 @@ __device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, in
 // A and B are loaded straight from global memory (one complex per lane per
 // block per K-step of 4) and double-buffered in registers: an fp64 MFMA runs
 // long enough on CDNA4 that operand traffic is small next to it.
-template <int WM, int WN, int WK, int BM, int BN>
+// TAG only separates the roles of the kernel in profiles (GW_KCLASS_*).
+template <int WM, int WN, int WK, int BM, int BN, int TAG>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const int lane = threadIdx.x & 63;
@@ -228,21 +229,35 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   }
 }
 
-template <int WM, int WN, int WK, int BM, int BN>
+template <int WM, int WN, int WK, int BM, int BN, int TAG>
 static hipError_t launch_cfg(const GemmDesc& d, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tiles = (long long)((d.M + TM - 1) / TM) * ((d.N + TN - 1) / TN);
   if (tiles > 0x7fffffffLL || d.batch > 65535) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)tiles, (unsigned)d.batch, 1);
-  zgemm_k<WM, WN, WK, BM, BN><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+  zgemm_k<WM, WN, WK, BM, BN, TAG><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
   return hipGetLastError();
+}
+
+template <int TAG>
+static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
+  if (d.M <= 32 && d.N <= 32) return launch_cfg<1, 1, 4, 2, 2, TAG>(d, st);
+  return launch_cfg<2, 2, 1, 2, 2, TAG>(d, st);
 }
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.K <= 0) return hipErrorInvalidValue;
-  if (d.M <= 32 && d.N <= 32) return launch_cfg<1, 1, 4, 2, 2>(d, st);
-  return launch_cfg<2, 2, 1, 2, 2>(d, st);
+  switch (d.tag) {
+    case KC_POL_CONTRACT: return launch_tag<KC_POL_CONTRACT>(d, st);
+    case KC_POL_PRODUCER: return launch_tag<KC_POL_PRODUCER>(d, st);
+    case KC_SE_CONTRACT: return launch_tag<KC_SE_CONTRACT>(d, st);
+    case KC_SE_PRODUCER: return launch_tag<KC_SE_PRODUCER>(d, st);
+    case KC_SE_FINAL: return launch_tag<KC_SE_FINAL>(d, st);
+    case KC_TRANSFORM: return launch_tag<KC_TRANSFORM>(d, st);
+    case KC_HF: return launch_tag<KC_HF>(d, st);
+    default: return launch_tag<0>(d, st);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -19,11 +19,14 @@ GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPA
 GW_FERMION, GW_BOSON = 0, 1
 GW_PREC_FP64 = 0
 GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF = range(4)
+KCLASS = dict(other=0, pol_contract=1, pol_producer=2, se_contract=3, se_producer=4,
+              se_final=5, transform=6, hf=7, wdyson=8, dyson=9)
 
 EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_workspace_bytes",
            "gw_set_workspace", "gw_polarization", "gw_tau_to_iw", "gw_iw_to_tau",
            "gw_screened_W", "gw_self_energy", "gw_density", "gw_hf", "gw_dyson_G",
-           "gw_find_mu", "gw_mix", "gw_grids_host", "gw_synchronize", "gw_status_string", "gw_last_error"]
+           "gw_find_mu", "gw_mix", "gw_grids_host", "gw_profile_enable", "gw_profile_read",
+           "gw_synchronize", "gw_status_string", "gw_last_error"]
 
 
 class GwError(RuntimeError):
@@ -68,6 +71,8 @@ def load():
         "gw_find_mu": ([P, P, P, P, P, D, D, P, P, P, P], I),
         "gw_synchronize": ([P], I),
         "gw_mix": ([P, LL, D, P, P, P], I),
+        "gw_profile_enable": ([P, I], I),
+        "gw_profile_read": ([P, I, P, P, P], I),
         "gw_grids_host": ([D, I, P, P, P, P, P, P, P, P, P, P], I),
         "gw_status_string": ([I], ctypes.c_char_p),
         "gw_last_error": ([P], ctypes.c_char_p),
@@ -293,3 +298,15 @@ def gw_find_mu(ctx, H0, S, Sig_inf, Sig_iw, n_target, mu0=0.0, tol=1e-13, G_iw=N
 
 def gw_synchronize(ctx):
     ctx._check(load().gw_synchronize(ctx.h), "gw_synchronize")
+
+
+def gw_profile_enable(ctx, on=True):
+    ctx._check(load().gw_profile_enable(ctx.h, 1 if on else 0), "gw_profile_enable")
+
+
+def gw_profile_read(ctx, kclass):
+    """(launches, milliseconds, algorithmic flops) of one kernel class."""
+    n, ms, fl = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+    ctx._check(load().gw_profile_read(ctx.h, int(kclass), ctypes.byref(n), ctypes.byref(ms),
+                                      ctypes.byref(fl)), "gw_profile_read")
+    return n.value, ms.value, fl.value
