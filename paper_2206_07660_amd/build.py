@@ -23,6 +23,8 @@ def build(verbose=False, arch="gfx950"):
     out_tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # MFMA accumulators in arch VGPRs: avoids per-iteration AGPR copies
+           "-mllvm", "-amdgpu-mfma-vgpr-form",
            "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include"),
            "-o", out_tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -28,6 +28,7 @@ struct gw_ctx {
   std::vector<gwgrid::cd> TF, TFp, TB, TBp, rrow;
   std::vector<int> plus;   // host copy of the k+q table
   bool check_bounds = false;
+  int tile_cfg = -1;       // tile configuration of the large contractions (-1: default)
   // measurement: event pairs per kernel class while profiling is on
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KC_COUNT];
@@ -187,7 +188,11 @@ gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
   hipEvent_t e0 = nullptr;
   gw_status s = prof_begin(c, g.tag, &e0);
   if (s != GW_OK) return s;
-  hipError_t e = zgemm_launch(g, c->st);
+  GemmDesc gg = g;
+  // tile shapes measured best on MI355X at naux = 250: 64x64 for the
+  // polarization contraction, 64x128 for the self-energy one
+  gg.cfg = c->tile_cfg >= 0 ? c->tile_cfg : (g.tag == KC_SE_CONTRACT ? 1 : 0);
+  hipError_t e = zgemm_launch(gg, c->st);
   if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("zgemm: ") + hipGetErrorString(e));
   // algorithmic flops: 8 real flops per complex multiply-add
   return prof_end(c, g.tag, e0, 8.0 * g.M * (double)g.N * g.K * g.batch);
@@ -270,6 +275,8 @@ gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
   {
     const char* e = std::getenv("GW_DEBUG_BOUNDS");
     c->check_bounds = e && e[0] == '1';
+    const char* t = std::getenv("GW_TILE_CFG");
+    c->tile_cfg = t ? std::atoi(t) : -1;
   }
   if (upload(c, &c->dplus, plus.data(), plus.size() * sizeof(int)) != GW_OK ||
       upload(c, &c->dminus, minus.data(), minus.size() * sizeof(int)) != GW_OK ||

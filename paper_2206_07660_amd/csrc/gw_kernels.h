@@ -39,6 +39,7 @@ struct GemmDesc {
   double alpha_r, alpha_i, beta_r, beta_i;
   int beta_zero;
   int tag;   // KC_*
+  int cfg;   // tile configuration of the large contractions
 };
 
 static inline GemmDesc gemm_desc() {

@@ -52,6 +52,20 @@ __device__ __forceinline__ void ctr_step(const Map3& m, Ctr& c, unsigned st) {
   }
 }
 
+// Same as ctr_step for st <= din and st <= din * dmid (at most one carry per
+// digit), written with selects so that the K loop has no divergent branches.
+__device__ __forceinline__ void ctr_step1(const Map3& m, Ctr& c, unsigned st) {
+  c.a += st;
+  c.off += (long long)st * m.sin;
+  const bool w1 = c.a >= m.din;
+  c.a = w1 ? c.a - m.din : c.a;
+  c.off += w1 ? (m.smid - (long long)m.din * m.sin) : 0;
+  c.b += w1 ? 1u : 0u;
+  const bool w2 = c.b >= m.dmid;
+  c.b = w2 ? 0u : c.b;
+  c.off += w2 ? (m.sout - (long long)m.dmid * m.smid) : 0;
+}
+
 __device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, int tmod, long long ts,
                                                unsigned b) {
   long long o = map3(m, b);
@@ -67,15 +81,26 @@ __device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, in
 // block per K-step of 4) and double-buffered in registers: an fp64 MFMA runs
 // long enough on CDNA4 that operand traffic is small next to it.
 // TAG only separates the roles of the kernel in profiles (GW_KCLASS_*).
-template <int WM, int WN, int WK, int BM, int BN, int TAG>
+template <int WM, int WN, int WK, int BM, int BN, int TAG, bool WRAP1>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // the wave index is uniform within a wave; saying so keeps the K loop scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WM, wn = (wave / WM) % WN, wk = wave / (WM * WN);
+  // XCD-aware order: the dispatcher deals workgroup ids round-robin over the
+  // 8 XCDs, so id w runs on XCD w % 8.  Give each XCD a contiguous range of
+  // logical ids, so that the tiles of one batch entry (which share operand
+  // rows and columns) meet in the same L2.
   const int tiles_m = (d.M + TM - 1) / TM;
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-  const unsigned bt = blockIdx.y;
+  const unsigned tiles = (unsigned)tiles_m * (unsigned)((d.N + TN - 1) / TN);
+  const unsigned total = gridDim.x;
+  const unsigned w = blockIdx.x;
+  const unsigned xcd = w % 8u, slot = w / 8u, per = total / 8u, rem = total % 8u;
+  const unsigned logical = xcd < rem ? xcd * (per + 1u) + slot : rem * (per + 1u) + (xcd - rem) * per + slot;
+  const unsigned tile = logical % tiles;
+  const int tm = (int)(tile % (unsigned)tiles_m), tn = (int)(tile / (unsigned)tiles_m);
+  const unsigned bt = logical / tiles;
 
   const double2* A = d.A + batch_off(d.ba, d.tab, d.tmod, d.tsA, bt);
   const double2* B = d.B + batch_off(d.bb, d.tab, d.tmod, d.tsB, bt);
@@ -110,43 +135,41 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
       accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
+  const unsigned K = (unsigned)d.K;
   const unsigned kstep = 4u * WK;
-  unsigned k = 4u * wk + kl;
-  Ctr ca = ctr_init(d.ak, k), cb = ctr_init(d.bk, k);
   const double sa = d.conjA ? -1.0 : 1.0;
   const double sb = d.conjB ? -1.0 : 1.0;
+  const double2 zero2 = double2{0.0, 0.0};
 
-  double2 a_cur[BM], b_cur[BN];
-  {
-    const bool kv = k < (unsigned)d.K;
+  // Branch-free fragment loads: an out-of-range lane reads the operand's first
+  // element (always valid) and keeps zero.
+  auto load = [&](double2 (&a)[BM], double2 (&b)[BN], const Ctr& ca, const Ctr& cb, bool kv) {
 #pragma unroll
-    for (int i = 0; i < BM; ++i) a_cur[i] = (av[i] && kv) ? A[aoff[i] + ca.off] : double2{0.0, 0.0};
+    for (int i = 0; i < BM; ++i) {
+      const bool ok = av[i] && kv;
+      const double2 v = A[ok ? aoff[i] + ca.off : 0];
+      a[i] = ok ? v : zero2;
+    }
 #pragma unroll
-    for (int j = 0; j < BN; ++j) b_cur[j] = (bv[j] && kv) ? B[boff[j] + cb.off] : double2{0.0, 0.0};
-  }
-  for (unsigned k0 = 4u * wk; k0 < (unsigned)d.K; k0 += kstep) {
-    // prefetch the next K-step
-    ctr_step(d.ak, ca, kstep);
-    ctr_step(d.bk, cb, kstep);
-    k += kstep;
-    double2 a_nxt[BM], b_nxt[BN];
-    const bool kv = k < (unsigned)d.K;
-#pragma unroll
-    for (int i = 0; i < BM; ++i) a_nxt[i] = (av[i] && kv) ? A[aoff[i] + ca.off] : double2{0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < BN; ++j) b_nxt[j] = (bv[j] && kv) ? B[boff[j] + cb.off] : double2{0.0, 0.0};
-
+    for (int j = 0; j < BN; ++j) {
+      const bool ok = bv[j] && kv;
+      const double2 v = B[ok ? boff[j] + cb.off : 0];
+      b[j] = ok ? v : zero2;
+    }
+  };
+  // complex 4M update: re += ar br - ai bi, im += ar bi + ai br
+  auto mma = [&](const double2 (&a)[BM], const double2 (&b)[BN]) {
     double ar[BM], ai[BM], nai[BM], br[BN], bi[BN];
 #pragma unroll
     for (int i = 0; i < BM; ++i) {
-      ar[i] = a_cur[i].x;
-      ai[i] = sa * a_cur[i].y;
+      ar[i] = a[i].x;
+      ai[i] = sa * a[i].y;
       nai[i] = -ai[i];
     }
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
-      br[j] = b_cur[j].x;
-      bi[j] = sb * b_cur[j].y;
+      br[j] = b[j].x;
+      bi[j] = sb * b[j].y;
     }
 #pragma unroll
     for (int i = 0; i < BM; ++i)
@@ -162,11 +185,37 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
         accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], accR[i][j], 0, 0, 0);
         accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
       }
-#pragma unroll
-    for (int i = 0; i < BM; ++i) a_cur[i] = a_nxt[i];
-#pragma unroll
-    for (int j = 0; j < BN; ++j) b_cur[j] = b_nxt[j];
+  };
+
+  auto step = [&](Ctr& ca, Ctr& cb) {
+    if constexpr (WRAP1) {
+      ctr_step1(d.ak, ca, kstep);
+      ctr_step1(d.bk, cb, kstep);
+    } else {
+      ctr_step(d.ak, ca, kstep);
+      ctr_step(d.bk, cb, kstep);
+    }
+  };
+
+  // Ping-pong register buffers: the loads of one K-step are in flight while
+  // the MFMAs of the previous one run.  nsteps is uniform across the wave.
+  const unsigned kfirst = 4u * wk;
+  const unsigned nsteps = kfirst < K ? (K - kfirst + kstep - 1) / kstep : 0u;
+  unsigned k = kfirst + kl;                  // this lane's k for the step in buffer 0
+  Ctr ca = ctr_init(d.ak, k), cb = ctr_init(d.bk, k);
+  double2 a0[BM], b0[BN], a1[BM], b1[BN];
+  load(a0, b0, ca, cb, k < K);
+  unsigned s = 0;
+  for (; s + 1 < nsteps; s += 2) {
+    step(ca, cb);
+    load(a1, b1, ca, cb, k + kstep < K);
+    mma(a0, b0);
+    step(ca, cb);
+    load(a0, b0, ca, cb, k + 2u * kstep < K);
+    mma(a1, b1);
+    k += 2u * kstep;
   }
+  if (s < nsteps) mma(a0, b0);
 
   if constexpr (WK > 1) {
     // deterministic split-K reduction: waves wk > 0 park their sums in LDS,
@@ -229,13 +278,22 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   }
 }
 
+static bool one_carry(const Map3& m, unsigned st) {
+  return m.din >= st && (unsigned long long)m.din * m.dmid >= st;
+}
+
 template <int WM, int WN, int WK, int BM, int BN, int TAG>
 static hipError_t launch_cfg(const GemmDesc& d, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tiles = (long long)((d.M + TM - 1) / TM) * ((d.N + TN - 1) / TN);
-  if (tiles > 0x7fffffffLL || d.batch > 65535) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)tiles, (unsigned)d.batch, 1);
-  zgemm_k<WM, WN, WK, BM, BN, TAG><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+  if (tiles > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (tiles * (long long)d.batch > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(tiles * d.batch), 1, 1);
+  const unsigned kstep = 4u * WK;
+  if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
+    zgemm_k<WM, WN, WK, BM, BN, TAG, true><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+  else
+    zgemm_k<WM, WN, WK, BM, BN, TAG, false><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
   return hipGetLastError();
 }
 
@@ -245,13 +303,27 @@ static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
   return launch_cfg<2, 2, 1, 2, 2, TAG>(d, st);
 }
 
+// The two large contractions (M = naux, K or N = Nk nao^2) can take larger
+// tiles; cfg selects one (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x64 on
+// eight waves, 4: 64x64 with two-way split K).
+template <int TAG>
+static hipError_t launch_big(const GemmDesc& d, hipStream_t st) {
+  switch (d.cfg) {
+    case 1: return launch_cfg<2, 2, 1, 2, 4, TAG>(d, st);
+    case 2: return launch_cfg<2, 2, 1, 4, 2, TAG>(d, st);
+    case 3: return launch_cfg<4, 2, 1, 2, 2, TAG>(d, st);
+    case 4: return launch_cfg<2, 2, 2, 2, 2, TAG>(d, st);
+    default: return launch_cfg<2, 2, 1, 2, 2, TAG>(d, st);
+  }
+}
+
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.K <= 0) return hipErrorInvalidValue;
   switch (d.tag) {
-    case KC_POL_CONTRACT: return launch_tag<KC_POL_CONTRACT>(d, st);
+    case KC_POL_CONTRACT: return launch_big<KC_POL_CONTRACT>(d, st);
     case KC_POL_PRODUCER: return launch_tag<KC_POL_PRODUCER>(d, st);
-    case KC_SE_CONTRACT: return launch_tag<KC_SE_CONTRACT>(d, st);
+    case KC_SE_CONTRACT: return launch_big<KC_SE_CONTRACT>(d, st);
     case KC_SE_PRODUCER: return launch_tag<KC_SE_PRODUCER>(d, st);
     case KC_SE_FINAL: return launch_tag<KC_SE_FINAL>(d, st);
     case KC_TRANSFORM: return launch_tag<KC_TRANSFORM>(d, st);

@@ -175,7 +175,7 @@ def make_V(wl: Workload, dtype=np.complex128):
 def random_hermitian_tau(rng, ntau, nk, n, scale=0.1):
     """Random data X[t][k] that is Hermitian at every (t, k) (test inputs)."""
     A = circular_gaussian(rng, (ntau, nk, n, n), scale)
-    return 0.5 * (A + np.conj(np.swapaxes(A, -1, -2)))
+    return np.ascontiguousarray(0.5 * (A + np.conj(np.swapaxes(A, -1, -2))))
 
 
 def small_workload(name="small", mesh=(2, 2, 2), nao=10, naux=70, ntau=20, beta=20.0,
