@@ -97,6 +97,53 @@ def cpu_baseline(wl, ntau_sample):
             "seconds_per_eval_extrapolated": t_eval}
 
 
+def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
+    """One Sigma+Pi evaluation from the current G in fp64 and in the mixed
+    path (complex64 V, fp32 MFMA contractions, fp64 elsewhere): seconds each
+    and the max-abs difference of Sigma_inf and Sigma~ in Ha."""
+    import torch
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.scgw import GWPath
+    G = st.G_tau
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s64_inf, s64_tau = path64.sigma(G)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    ref_inf, ref_tau = s64_inf.clone(), s64_tau.clone()
+    V32 = V.to(torch.complex64)
+    ctx32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision="fp32")
+    p32 = GWPath(ctx32, V32, H0, S, wl.n_target)
+    p32.sigma(G)                                   # warm-up
+    torch.cuda.synchronize()
+    gw.gw_profile_enable(ctx32, True)
+    t0 = time.perf_counter()
+    s32_inf, s32_tau = p32.sigma(G)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    prof = {n: gw.gw_profile_read(ctx32, kc) for n, kc in gw.KCLASS.items()}
+    gw.gw_profile_enable(ctx32, False)
+    e_inf = (s32_inf - ref_inf).abs().max().item()
+    e_tau = (s32_tau - ref_tau).abs().max().item()
+    flops = contraction_flops(wl.nk, wl.nao, wl.naux, wl.ntau)
+    n_l, ms_l, fl_l = prof["pol_contract"]
+    res = {"sigma_eval_s_fp64": t64, "sigma_eval_s_mixed": t32, "speedup": t64 / t32,
+           "evals_per_s_mixed": 1.0 / t32,
+           "gflops_contractions_mixed": flops / t32 / 1e9,
+           "fp32_mfma_frac_path": flops / t32 / 157.3e12,
+           "pol_contract_tflops_mixed": fl_l / (ms_l * 1e-3) / 1e12 if ms_l else None,
+           "max_abs_dSigma_inf_Ha": e_inf, "max_abs_dSigma_tilde_Ha": e_tau,
+           "kernel_ms": {k: round(v[1], 2) for k, v in prof.items() if v[0]},
+           "precision": "V complex64, G rounded to complex64, fp32 MFMA with fp64 chunk sums; "
+                        "transforms, screened-interaction solve, HF, Dyson, mu in fp64"}
+    ctx32.close()
+    del V32, p32
+    torch.cuda.empty_cache()
+    log(f"[bench] mixed: {t32:.2f} s vs fp64 {t64:.2f} s per Sigma+Pi evaluation, "
+        f"max|dSigma| {max(e_inf, e_tau):.2e} Ha")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +152,8 @@ def main():
     ap.add_argument("--workload", default="si-4x4x4")
     ap.add_argument("--cpu-sample-tau", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision (fp32 MFMA) comparison")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -197,6 +246,8 @@ def main():
                      "flops_per_launch": fl_l / max(n_l, 1)},
         "history": hist,
     }
+    if not args.no_mixed:
+        out["mixed_fp32"] = mixed_comparison(ctx, path, st, V, H0, S, wl)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_tau)

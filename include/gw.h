@@ -63,8 +63,18 @@ typedef enum {
 
 enum { GW_FERMION = 0, GW_BOSON = 1 };
 
-/* Contraction precision of the polarization and self-energy chains. */
-enum { GW_PREC_FP64 = 0 };
+/* Contraction precision of the polarization and self-energy chains.
+ * GW_PREC_FP64: everything in fp64, V complex128.
+ * GW_PREC_FP32: mixed precision.  V is stored complex64 (gw_c); in
+ *   gw_polarization and gw_self_energy G is rounded to complex64, the
+ *   products run as complex fp32 MFMA GEMMs with their intermediates in
+ *   complex64, and the long contraction sums add each 512-term chunk
+ *   accumulated in fp32 into fp64; their outputs (P0, Sigma~) are
+ *   complex128.  gw_hf reads the complex64 V in fp64 arithmetic; the
+ *   transforms, both Dyson solves and the mu search are fp64 as in
+ *   GW_PREC_FP64.                                                           */
+enum { GW_PREC_FP64 = 0, GW_PREC_FP32 = 1 };
+typedef struct { float re, im; } gw_c;
 
 typedef struct {
   int mesh[3];     /* n1, n2, n3 >= 1; Nk = n1 n2 n3                          */
@@ -134,8 +144,8 @@ gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
  *   P0^q_{QQ'}(tau_i) = -(ns/Nk) sum_k sum_{abcd} V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_i)
  *                       V^{k+q,k}_{bc}(Q') G^k_{cd}(tau_{ntau-1-i})
  * for q = q0 .. q0+nq-1, written to P0_tau[q-q0][i] (overwritten).          */
-gw_status gw_polarization(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, int q0, int nq,
-                          gw_z* P0_tau);
+gw_status gw_polarization(gw_ctx* ctx, const void* V, const gw_z* G_tau, int q0, int nq,
+                          gw_z* P0_tau);   /* V: gw_z (GW_PREC_FP64) or gw_c (GW_PREC_FP32) */
 
 /* Eqs. tau_to_iw / P0t_to_P0w: X_iw[b][n][r] = sum_i T[n][i] X_tau[b][i][r]
  * for b < batch, r < R, with T the fermionic (stat = GW_FERMION, nw = nw_f)
@@ -159,8 +169,8 @@ gw_status gw_screened_W(gw_ctx* ctx, const gw_z* P0_iw, int nq, gw_z* Pt_iw);
  *   Sig_tau^k_{ij}(tau) += -(1/Nk) sum_q sum_{ab} sum_{QQ'} G^{k-q}_{ab}(tau)
  *                          V^{k,k-q}_{ia}(Q) P~^q_{QQ'}(tau) V^{k-q,k}_{bj}(Q')
  * Callers zero Sig_tau before the first q-batch.                            */
-gw_status gw_self_energy(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* Pt_tau,
-                         int q0, int nq, gw_z* Sig_tau);
+gw_status gw_self_energy(gw_ctx* ctx, const void* V, const gw_z* G_tau, const gw_z* Pt_tau,
+                         int q0, int nq, gw_z* Sig_tau);   /* V as in gw_polarization */
 
 /* Density matrix and electron count (Sec. III): gamma^k = -G^k(beta^-) =
  * -sum_i w_i G^k(tau_i); N_e = (ns/Nk) sum_k Re tr[gamma^k S^k].  gamma is a
@@ -171,7 +181,7 @@ gw_status gw_density(gw_ctx* ctx, const gw_z* G_tau, const gw_z* S, gw_z* gamma,
  *   J^k = sum_Q v_Q V^{kk}(Q),  v_Q = (ns/Nk) sum_k' tr[gamma^k' V^{k'k'}(Q)]
  *   K^k = -(1/Nk) sum_q sum_Q V^{k,k+q}(Q) gamma^{k+q} V^{k+q,k}(Q)
  * Sig_inf = J + K is overwritten; gamma (may be NULL) receives gamma.        */
-gw_status gw_hf(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, gw_z* gamma, gw_z* Sig_inf);
+gw_status gw_hf(gw_ctx* ctx, const void* V, const gw_z* G_tau, gw_z* gamma, gw_z* Sig_inf);
 
 /* Eq. Dyson: G^k(i w_n) = [(i w_n + mu) S^k - H0^k - Sig_inf^k - Sig_iw^k(i w_n)]^{-1}
  * for every sparse fermionic n and every k, by Gauss-Jordan elimination with

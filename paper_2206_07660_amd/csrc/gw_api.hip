@@ -79,7 +79,10 @@ gw_status check_dims(const gw_dims* d, std::string& why) {
   if (d->nw_b != d->ntau + 1) { why = "nw_b must equal ntau + 1"; return GW_ERR_ARG; }
   if (d->ns != 1 && d->ns != 2) { why = "ns must be 1 or 2"; return GW_ERR_ARG; }
   if (!(d->beta > 0.0) || !std::isfinite(d->beta)) { why = "beta must be positive"; return GW_ERR_ARG; }
-  if (d->precision != GW_PREC_FP64) { why = "unsupported precision"; return GW_ERR_ARG; }
+  if (d->precision != GW_PREC_FP64 && d->precision != GW_PREC_FP32) {
+    why = "unsupported precision";
+    return GW_ERR_ARG;
+  }
   const long long nk = (long long)d->mesh[0] * d->mesh[1] * d->mesh[2];
   if (nk * d->nao * (long long)d->nao * d->naux > (1LL << 31)) {
     why = "Nk * naux * nao^2 must stay below 2^31";
@@ -426,6 +429,9 @@ size_t gw_workspace_bytes(const gw_ctx* c, int op, int tau_chunk) {
     case GW_OP_POLARIZATION:
     case GW_OP_SELF_ENERGY:
       if (tau_chunk < 1 || tau_chunk > c->d.ntau) return 0;
+      if (c->d.precision == GW_PREC_FP32)   // complex64 intermediates + complex64 copy of G
+        return 2 * align256((size_t)tau_chunk * c->nk * c->sv * 8) +
+               align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
       return 2 * align256((size_t)tau_chunk * c->nk * c->sv * z);
     case GW_OP_SCREENED_W:
       if (tau_chunk < 1) return 0;
@@ -513,7 +519,20 @@ gw_status gw_synchronize(gw_ctx* c) {
 }
 
 // ------------------------------------------------------------- Eq. tilde_P0_tau
-gw_status gw_polarization(gw_ctx* c, const gw_z* V, const gw_z* G, int q0, int nq, gw_z* P0) {
+// Mixed-precision context: V and the chain intermediates are complex64, G is
+// rounded to complex64 once per call, the MFMAs run in fp32 and the long
+// contractions add each 512-element chunk of their K sum into fp64.
+static const int kMixedChunk = 512;
+
+// complex64 copy of G(tau) in the workspace (mixed precision only)
+static gw_status g_to_c64(gw_ctx* c, const gw_z* G, void** Gc) {
+  const size_t off = 2 * align256((size_t)c->tc * c->nk * c->sv * 8);
+  *Gc = (char*)c->ws + off;
+  HIPCHK(c, to_c64_launch((const double2*)G, (float2*)*Gc, (long long)c->d.ntau * c->nk * c->n2, c->st));
+  return GW_OK;
+}
+
+gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int nq, gw_z* P0) {
   if (!c) return GW_ERR_ARG;
   if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
   if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
@@ -525,34 +544,45 @@ gw_status gw_polarization(gw_ctx* c, const gw_z* V, const gw_z* G, int q0, int n
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv;
   const long long S = (long long)nk * sv;                // one tau slice of X or Zt
-  double2* X = (double2*)c->ws;
-  double2* Z = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
-  const double2* Vd = (const double2*)V;
-  const double2* Gd = (const double2*)G;
+  const bool f32 = c->d.precision == GW_PREC_FP32;
+  const size_t ez = f32 ? 8 : 16;                        // bytes of V / X / Zt / G elements
+  char* X = (char*)c->ws;
+  char* Z = (char*)c->ws + align256((size_t)tc * S * ez);
+  const char* Vd = (const char*)V;
+  const char* Gd = (const char*)G;
+  if (f32) {
+    void* Gc = nullptr;
+    gw_status s = g_to_c64(c, G, &Gc);
+    if (s != GW_OK) return s;
+    Gd = (const char*)Gc;
+  }
+  const int t = f32 ? 1 : 0;
   for (int q = q0; q < q0 + nq; ++q) {
+    const char* Aq = Vd + (size_t)q * nk * sv * ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {
       const int tcur = std::min(tc, nt - t0);
       // X[tl][k][Q][d][b] = sum_a V[q][k][Q][d][a] G[t0+tl][k+q][a][b]
-      const double2* Aq = Vd + (long long)q * nk * sv;
       GemmDesc g = gemm_desc();
-      g.A = Aq; g.B = Gd + (long long)t0 * nk * n2; g.C = X;
+      g.A = Aq; g.B = Gd + (size_t)t0 * nk * n2 * ez; g.C = X;
       g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
       g.am = aff(nao); g.ak = aff(1);
       g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
       g.cm = aff(nao); g.cn = two(nao, 1, S);
       g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;   // G^{k+q}
+      g.ta = g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_POL_PRODUCER;
       gw_status s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * S});
       if (s != GW_OK) return s;
       // Zt[tl][k][Q'][d][b] = sum_c G[nt-1-t0-tl][k][c][d] conj(V[q][k][Q'][c][b])
       g = gemm_desc();
-      g.A = Gd + (long long)(nt - 1 - t0) * nk * n2; g.B = Aq; g.C = Z;
+      g.A = Gd + (size_t)(nt - 1 - t0) * nk * n2 * ez; g.B = Aq; g.C = Z;
       g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
       g.am = two(nao, 1, -(long long)nk * n2); g.ak = aff(nao);
       g.bk = aff(nao); g.bn = two(nao, 1, n2); g.conjB = 1;
       g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
       g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
+      g.ta = g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_POL_PRODUCER;
       if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tc * S})) != GW_OK) return s;
       // P0[q-q0][t0+tl][Q][Q'] = -(ns/nk) sum_{k,e} X[tl][k][Q][e] Zt[tl][k][Q'][e]
@@ -564,6 +594,7 @@ gw_status gw_polarization(gw_ctx* c, const gw_z* V, const gw_z* G, int q0, int n
       g.cm = aff(naux); g.cn = aff(1);
       g.ba = aff(S); g.bb = aff(S); g.bc = aff((long long)naux * naux);
       g.alpha_r = -(double)c->d.ns / nk;
+      g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = f32 ? kMixedChunk : 0;
       g.tag = KC_POL_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * naux * naux})) != GW_OK) return s;
     }
@@ -629,7 +660,7 @@ gw_status gw_screened_W(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt) {
 }
 
 // ------------------------------------------------------------- Eq. tilde_sigma2
-gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt, int q0, int nq,
+gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt, int q0, int nq,
                          gw_z* Sig) {
   if (!c) return GW_ERR_ARG;
   if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
@@ -642,12 +673,21 @@ gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv;
   const long long S = (long long)nk * sv;
-  double2* Vt = (double2*)c->ws;
-  double2* L = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
-  const double2* Vd = (const double2*)V;
-  const double2* Gd = (const double2*)G;
+  const bool f32 = c->d.precision == GW_PREC_FP32;
+  const size_t ez = f32 ? 8 : 16;
+  char* Vt = (char*)c->ws;
+  char* L = (char*)c->ws + align256((size_t)tc * S * ez);
+  const char* Vd = (const char*)V;
+  const char* Gd = (const char*)G;
+  if (f32) {
+    void* Gc = nullptr;
+    gw_status s = g_to_c64(c, G, &Gc);
+    if (s != GW_OK) return s;
+    Gd = (const char*)Gc;
+  }
+  const int t = f32 ? 1 : 0;
   for (int q = q0; q < q0 + nq; ++q) {
-    const double2* Aq = Vd + (long long)q * nk * sv;
+    const char* Aq = Vd + (size_t)q * nk * sv * ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {
       const int tcur = std::min(tc, nt - t0);
       // Vt[tl][Q][kk][b][j] = sum_Q' Pt[q][t0+tl][Q][Q'] V[q][kk][Q'][b][j]
@@ -659,17 +699,19 @@ gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt
       g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
       g.cm = aff((long long)nk * n2); g.cn = aff(1);
       g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
+      g.ta = 0; g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_SE_CONTRACT;
       gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
       if (s != GW_OK) return s;
       // L[tl][kk][Q][i][b] = sum_a conj(V[q][kk][Q][a][i]) G[t0+tl][kk][a][b]
       g = gemm_desc();
-      g.A = Aq; g.B = Gd + (long long)t0 * nk * n2; g.C = L;
+      g.A = Aq; g.B = Gd + (size_t)t0 * nk * n2 * ez; g.C = L;
       g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
       g.am = two(nao, 1, n2); g.ak = aff(nao); g.conjA = 1;
       g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
       g.cm = aff(nao); g.cn = two(nao, 1, S);
       g.ba = aff(sv); g.bb = aff(n2); g.bc = aff(sv);
+      g.ta = g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_SE_PRODUCER;
       if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
       // Sig[t0+tl][kk+q][i][j] += -(1/nk) sum_{Q,b} L[tl][kk][Q][i][b] Vt[tl][Q][kk][b][j]
@@ -683,6 +725,7 @@ gw_status gw_self_energy(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
       g.alpha_r = -1.0 / nk;
       g.beta_zero = 0; g.beta_r = 1.0;
+      g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = f32 ? kMixedChunk : 0;
       g.tag = KC_SE_FINAL;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * nk * n2})) != GW_OK) return s;
     }
@@ -716,7 +759,7 @@ gw_status gw_density(gw_ctx* c, const gw_z* G, const gw_z* S, gw_z* gamma, doubl
 }
 
 // ------------------------------------------------------------- Eqs. HF_J, HF_K
-gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* Sinf) {
+gw_status gw_hf(gw_ctx* c, const void* V, const gw_z* G, gw_z* gamma_out, gw_z* Sinf) {
   if (!c) return GW_ERR_ARG;
   if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
   if (!V || !G || !Sinf) return fail(c, GW_ERR_ARG, "NULL array");
@@ -728,7 +771,9 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
   double2* gam = (double2*)((char*)c->ws + align256((size_t)nk * sv * 16));
   double2* vq = (double2*)((char*)gam + align256((size_t)nk * n2 * 16));
   if (gamma_out) gam = (double2*)gamma_out;
-  const double2* Vd = (const double2*)V;
+  const char* Vd = (const char*)V;
+  const int tv = c->d.precision == GW_PREC_FP32 ? 1 : 0;   // V storage type
+  const size_t ez = tv ? 8 : 16;
   gw_status s = gamma_of(c, G, gam);
   if (s != GW_OK) return s;
   // v[Q] = (ns/nk) sum_{k',b,a} V[0][k'][Q][b][a] gamma[k'][a][b]
@@ -739,6 +784,7 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
   g.bk = three(nao, nao, nao, 1, n2); g.bn = aff(0);
   g.cm = aff(1); g.cn = aff(0);
   g.alpha_r = (double)c->d.ns / nk;
+  g.ta = tv;
   g.tag = KC_HF;
   if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)naux})) != GW_OK) return s;
   // J[k][e] = sum_Q v[Q] V[0][k][Q][e]
@@ -748,10 +794,11 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
   g.am = aff(0); g.ak = aff(1);
   g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
   g.cm = aff(0); g.cn = aff(1);
+  g.tb = tv;
   g.tag = KC_HF;
   if ((s = run(c, g, Ext{0, (long long)naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
   for (int q = 0; q < nk; ++q) {
-    const double2* Aq = Vd + (long long)q * nk * sv;
+    const char* Aq = Vd + (size_t)q * nk * sv * ez;
     // T1[k][Q][i][b] = sum_a V[q][k][Q][i][a] gamma[k+q][a][b]
     g = gemm_desc();
     g.A = Aq; g.B = gam; g.C = T1;
@@ -760,6 +807,7 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
     g.cm = aff(nao); g.cn = aff(1);
     g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
     g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;
+    g.ta = tv;
     g.tag = KC_HF;
     if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)nk * sv})) != GW_OK) return s;
     // Sinf[k][i][j] += -(1/nk) sum_{Q,b} T1[k][Q][i][b] conj(V[q][k][Q][j][b])
@@ -772,6 +820,7 @@ gw_status gw_hf(gw_ctx* c, const gw_z* V, const gw_z* G, gw_z* gamma_out, gw_z* 
     g.ba = aff(sv); g.bb = aff(sv); g.bc = aff(n2);
     g.alpha_r = -1.0 / nk;
     g.beta_zero = 0; g.beta_r = 1.0;
+    g.tb = tv;
     g.tag = KC_HF;
     if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
   }

@@ -19,16 +19,16 @@ static inline Map3 three(unsigned din, long long sin, unsigned dmid, long long s
 
 // C[b](m, n) = alpha * sum_k op(A)[b](m, k) * op(B)[b](k, n) + beta * C[b](m, n)
 // with A[b](m, k) = A[ba(b) + tab[b % tmod] * tsA + am(m) + ak(k)] (conjugated if conjA),
-// and likewise for B and C.  Offsets count complex elements.
+// and likewise for B and C.  Offsets count complex elements of the operand's type.
 // Kernel classes (profiling roles); values match GW_KCLASS_* of gw.h.
 enum { KC_OTHER = 0, KC_POL_CONTRACT = 1, KC_POL_PRODUCER = 2, KC_SE_CONTRACT = 3,
        KC_SE_PRODUCER = 4, KC_SE_FINAL = 5, KC_TRANSFORM = 6, KC_HF = 7, KC_WDYSON = 8,
        KC_DYSON = 9, KC_COUNT = 10 };
 
 struct GemmDesc {
-  const double2* A;
-  const double2* B;
-  double2* C;
+  const void* A;   // element type by ta: 0 complex128 (double2), 1 complex64 (float2)
+  const void* B;   // tb
+  void* C;         // tc
   int M, N, K, batch;
   Map3 am, ak, bk, bn, cm, cn;
   Map3 ba, bb, bc;
@@ -40,6 +40,9 @@ struct GemmDesc {
   int beta_zero;
   int tag;   // KC_*
   int cfg;   // tile configuration of the large contractions
+  int ta, tb, tc;   // storage types of A, B, C (0 complex128, 1 complex64)
+  int f32;          // 1: fp32 MFMA with fp64 promotion every kchunk K-elements
+  int kchunk;
 };
 
 static inline GemmDesc gemm_desc() {
@@ -77,3 +80,4 @@ hipError_t trace_launch(const double2* g, const double2* S, int n, int nk, doubl
 hipError_t mix_launch(long long n, double alpha, const double2* X, double2* Y, double* part,
                       int nblk, hipStream_t st);
 hipError_t zero_flag_launch(int* p, hipStream_t st);
+hipError_t to_c64_launch(const double2* x, float2* y, long long n, hipStream_t st);

@@ -9,9 +9,12 @@
 //                with the electron-count partials of gamma = -G(beta^-).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gw_kernels.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ long long map3(const Map3& m, unsigned i) {
   unsigned a = i % m.din;
@@ -74,15 +77,58 @@ __device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, in
 }
 
 // ---------------------------------------------------------------------------
-// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b], complex.
 // Waves: WM x WN tile the output, WK split the K loop (reduced through LDS).
 // Each wave owns BM x BN blocks of 16 x 16 complex outputs.  The fragments of
 // A and B are loaded straight from global memory (one complex per lane per
-// block per K-step of 4) and double-buffered in registers: an fp64 MFMA runs
-// long enough on CDNA4 that operand traffic is small next to it.
-// TAG only separates the roles of the kernel in profiles (GW_KCLASS_*).
-template <int WM, int WN, int WK, int BM, int BN, int TAG, bool WRAP1>
+// block per K-step of 4) into a two-stage register ping-pong.
+// TA, TB, TC are the storage types (double2 = complex128, float2 = complex64).
+// F32 = false: v_mfma_f64_16x16x4_f64, fp64 accumulation.
+// F32 = true:  v_mfma_f32_16x16x4_f32 on operands rounded to fp32, fp32
+//              accumulation inside chunks of d.kchunk K-elements, each chunk
+//              added into fp64 accumulators.
+// TAG only separates the roles of the kernel in profiles (KC_*).
+
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return double2{(double)v.x, (double)v.y}; }
+__device__ __forceinline__ float2 to_f2(double2 v) { return float2{(float)v.x, (float)v.y}; }
+__device__ __forceinline__ float2 to_f2(float2 v) { return v; }
+template <class T> __device__ __forceinline__ T from_d2(double2 v);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) {
+  return float2{(float)v.x, (float)v.y};
+}
+
+template <bool F32> struct Mfma;
+template <> struct Mfma<false> {
+  typedef double S;
+  typedef double2 S2;
+  typedef d4 Acc;
+  static __device__ __forceinline__ Acc run(S a, S b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  template <class T> static __device__ __forceinline__ S2 cvt(T v) { return to_d2(v); }
+  // output row of accumulator element r held by lane group g = lane / 16
+  static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+template <> struct Mfma<true> {
+  typedef float S;
+  typedef float2 S2;
+  typedef f4 Acc;
+  static __device__ __forceinline__ Acc run(S a, S b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  template <class T> static __device__ __forceinline__ S2 cvt(T v) { return to_f2(v); }
+  static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+
+template <int WM, int WN, int WK, int BM, int BN, int TAG, bool WRAP1, class TA, class TB, class TC,
+          bool F32>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
+  typedef Mfma<F32> MM;
+  typedef typename MM::S S;
+  typedef typename MM::S2 S2;
+  typedef typename MM::Acc Acc;
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const int lane = threadIdx.x & 63;
   // the wave index is uniform within a wave; saying so keeps the K loop scalar
@@ -102,9 +148,9 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   const int tm = (int)(tile % (unsigned)tiles_m), tn = (int)(tile / (unsigned)tiles_m);
   const unsigned bt = logical / tiles;
 
-  const double2* A = d.A + batch_off(d.ba, d.tab, d.tmod, d.tsA, bt);
-  const double2* B = d.B + batch_off(d.bb, d.tab, d.tmod, d.tsB, bt);
-  double2* C = d.C + batch_off(d.bc, d.tab, d.tmod, d.tsC, bt);
+  const TA* A = (const TA*)d.A + batch_off(d.ba, d.tab, d.tmod, d.tsA, bt);
+  const TB* B = (const TB*)d.B + batch_off(d.bb, d.tab, d.tmod, d.tsB, bt);
+  TC* C = (TC*)d.C + batch_off(d.bc, d.tab, d.tmod, d.tsC, bt);
 
   const int m0 = tm * TM + wm * BM * 16;
   const int n0 = tn * TN + wn * BN * 16;
@@ -126,40 +172,65 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     boff[j] = bv[j] ? map3(d.bn, n) : 0;
   }
 
-  d4 accR[BM][BN], accI[BM][BN];
+  Acc accR[BM][BN], accI[BM][BN];
+  double sumR[F32 ? BM : 1][F32 ? BN : 1][4], sumI[F32 ? BM : 1][F32 ? BN : 1][4];
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
-      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accR[i][j] = Acc{0, 0, 0, 0};
+      accI[i][j] = Acc{0, 0, 0, 0};
     }
+  if constexpr (F32) {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sumR[i][j][r] = sumI[i][j][r] = 0.0;
+  }
+  auto promote = [&]() {
+    if constexpr (F32) {
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            sumR[i][j][r] += (double)accR[i][j][r];
+            sumI[i][j][r] += (double)accI[i][j][r];
+          }
+          accR[i][j] = Acc{0, 0, 0, 0};
+          accI[i][j] = Acc{0, 0, 0, 0};
+        }
+    }
+  };
 
   const unsigned K = (unsigned)d.K;
   const unsigned kstep = 4u * WK;
-  const double sa = d.conjA ? -1.0 : 1.0;
-  const double sb = d.conjB ? -1.0 : 1.0;
-  const double2 zero2 = double2{0.0, 0.0};
+  const S sa = d.conjA ? S(-1) : S(1);
+  const S sb = d.conjB ? S(-1) : S(1);
+  const S2 zero2 = S2{0, 0};
 
   // Branch-free fragment loads: an out-of-range lane reads the operand's first
   // element (always valid) and keeps zero.
-  auto load = [&](double2 (&a)[BM], double2 (&b)[BN], const Ctr& ca, const Ctr& cb, bool kv) {
+  auto load = [&](S2 (&a)[BM], S2 (&b)[BN], const Ctr& ca, const Ctr& cb, bool kv) {
 #pragma unroll
     for (int i = 0; i < BM; ++i) {
       const bool ok = av[i] && kv;
-      const double2 v = A[ok ? aoff[i] + ca.off : 0];
+      const S2 v = MM::cvt(A[ok ? aoff[i] + ca.off : 0]);
       a[i] = ok ? v : zero2;
     }
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
       const bool ok = bv[j] && kv;
-      const double2 v = B[ok ? boff[j] + cb.off : 0];
+      const S2 v = MM::cvt(B[ok ? boff[j] + cb.off : 0]);
       b[j] = ok ? v : zero2;
     }
   };
   // complex 4M update: re += ar br - ai bi, im += ar bi + ai br
-  auto mma = [&](const double2 (&a)[BM], const double2 (&b)[BN]) {
-    double ar[BM], ai[BM], nai[BM], br[BN], bi[BN];
+  auto mma = [&](const S2 (&a)[BM], const S2 (&b)[BN]) {
+    S ar[BM], ai[BM], nai[BM], br[BN], bi[BN];
 #pragma unroll
     for (int i = 0; i < BM; ++i) {
       ar[i] = a[i].x;
@@ -175,18 +246,17 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
-        accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+        accR[i][j] = MM::run(ar[i], br[j], accR[i][j]);
+        accI[i][j] = MM::run(ar[i], bi[j], accI[i][j]);
       }
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], accR[i][j], 0, 0, 0);
-        accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+        accR[i][j] = MM::run(nai[i], bi[j], accR[i][j]);
+        accI[i][j] = MM::run(ai[i], br[j], accI[i][j]);
       }
   };
-
   auto step = [&](Ctr& ca, Ctr& cb) {
     if constexpr (WRAP1) {
       ctr_step1(d.ak, ca, kstep);
@@ -198,24 +268,46 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   };
 
   // Ping-pong register buffers: the loads of one K-step are in flight while
-  // the MFMAs of the previous one run.  nsteps is uniform across the wave.
+  // the MFMAs of the previous one run.  nsteps and the promotion period are
+  // uniform across the wave.
   const unsigned kfirst = 4u * wk;
   const unsigned nsteps = kfirst < K ? (K - kfirst + kstep - 1) / kstep : 0u;
+  const unsigned cper = F32 && d.kchunk > 0 ? (unsigned)d.kchunk / kstep : 0u;
   unsigned k = kfirst + kl;                  // this lane's k for the step in buffer 0
   Ctr ca = ctr_init(d.ak, k), cb = ctr_init(d.bk, k);
-  double2 a0[BM], b0[BN], a1[BM], b1[BN];
+  S2 a0[BM], b0[BN], a1[BM], b1[BN];
   load(a0, b0, ca, cb, k < K);
   unsigned s = 0;
   for (; s + 1 < nsteps; s += 2) {
     step(ca, cb);
     load(a1, b1, ca, cb, k + kstep < K);
     mma(a0, b0);
+    if (cper && (s + 1) % cper == 0) promote();
     step(ca, cb);
     load(a0, b0, ca, cb, k + 2u * kstep < K);
     mma(a1, b1);
+    if (cper && (s + 2) % cper == 0) promote();
     k += 2u * kstep;
   }
   if (s < nsteps) mma(a0, b0);
+  promote();
+
+  // lane-local result, fp64
+  auto res = [&](int i, int j, int r, bool im) -> double {
+    if constexpr (F32) return im ? sumI[i][j][r] : sumR[i][j][r];
+    else return im ? accI[i][j][r] : accR[i][j][r];
+  };
+
+  double outR[BM][BN][4], outI[BM][BN][4];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        outR[i][j][r] = res(i, j, r, false);
+        outI[i][j][r] = res(i, j, r, true);
+      }
 
   if constexpr (WK > 1) {
     // deterministic split-K reduction: waves wk > 0 park their sums in LDS,
@@ -230,28 +322,28 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
         for (int j = 0; j < BN; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            p[(slot + ((i * BN + j) * 8 + r)) * 64 + lane] = accR[i][j][r];
-            p[(slot + ((i * BN + j) * 8 + 4 + r)) * 64 + lane] = accI[i][j][r];
+            p[(slot + ((i * BN + j) * 8 + r)) * 64 + lane] = outR[i][j][r];
+            p[(slot + ((i * BN + j) * 8 + 4 + r)) * 64 + lane] = outI[i][j][r];
           }
     }
     __syncthreads();
     if (wk > 0) return;
-    for (int w = 1; w < WK; ++w) {
-      const double* p = red + ((size_t)(w - 1) * WM * WN * BM * BN * 8) * 64;
+    for (int w2 = 1; w2 < WK; ++w2) {
+      const double* p = red + ((size_t)(w2 - 1) * WM * WN * BM * BN * 8) * 64;
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
         for (int j = 0; j < BN; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            accR[i][j][r] += p[(slot + ((i * BN + j) * 8 + r)) * 64 + lane];
-            accI[i][j][r] += p[(slot + ((i * BN + j) * 8 + 4 + r)) * 64 + lane];
+            outR[i][j][r] += p[(slot + ((i * BN + j) * 8 + r)) * 64 + lane];
+            outI[i][j][r] += p[(slot + ((i * BN + j) * 8 + 4 + r)) * 64 + lane];
           }
     }
   }
 
-  // epilogue: for v_mfma_f64_16x16x4_f64 lane l holds column l%16 and rows
-  // l/16 + 4r (r = 0..3) of each 16 x 16 block
+  // epilogue: lane holds column lane%16 of each 16 x 16 block and the rows
+  // given by MM::row (f64 MFMA: lane/16 + 4r; f32 MFMA: 4 (lane/16) + r)
 #pragma unroll
   for (int j = 0; j < BN; ++j) {
     const int n = n0 + j * 16 + r16;
@@ -261,19 +353,19 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + i * 16 + kl + 4 * r;
+        const int m = m0 + i * 16 + MM::row(kl, r);
         if (m >= d.M) continue;
         const long long o = map3(d.cm, m) + con;
-        const double xr = accR[i][j][r], xi = accI[i][j][r];
+        const double xr = outR[i][j][r], xi = outI[i][j][r];
         double2 v;
         v.x = d.alpha_r * xr - d.alpha_i * xi;
         v.y = d.alpha_r * xi + d.alpha_i * xr;
         if (!d.beta_zero) {
-          const double2 c = C[o];
+          const double2 c = to_d2(C[o]);
           v.x += d.beta_r * c.x - d.beta_i * c.y;
           v.y += d.beta_r * c.y + d.beta_i * c.x;
         }
-        C[o] = v;
+        C[o] = from_d2<TC>(v);
       }
   }
 }
@@ -282,7 +374,7 @@ static bool one_carry(const Map3& m, unsigned st) {
   return m.din >= st && (unsigned long long)m.din * m.dmid >= st;
 }
 
-template <int WM, int WN, int WK, int BM, int BN, int TAG>
+template <int WM, int WN, int WK, int BM, int BN, int TAG, class TA, class TB, class TC, bool F32>
 static hipError_t launch_cfg(const GemmDesc& d, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tiles = (long long)((d.M + TM - 1) / TM) * ((d.N + TN - 1) / TN);
@@ -290,40 +382,64 @@ static hipError_t launch_cfg(const GemmDesc& d, hipStream_t st) {
   if (tiles * (long long)d.batch > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(tiles * d.batch), 1, 1);
   const unsigned kstep = 4u * WK;
+  if (F32 && d.kchunk > 0 && d.kchunk % kstep) return hipErrorInvalidValue;
   if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
-    zgemm_k<WM, WN, WK, BM, BN, TAG, true><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+    zgemm_k<WM, WN, WK, BM, BN, TAG, true, TA, TB, TC, F32><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
   else
-    zgemm_k<WM, WN, WK, BM, BN, TAG, false><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+    zgemm_k<WM, WN, WK, BM, BN, TAG, false, TA, TB, TC, F32><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
   return hipGetLastError();
 }
 
-template <int TAG>
-static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
-  if (d.M <= 32 && d.N <= 32) return launch_cfg<1, 1, 4, 2, 2, TAG>(d, st);
-  return launch_cfg<2, 2, 1, 2, 2, TAG>(d, st);
+// Tile shape: 32 x 32 with four-way split K for small outputs; otherwise
+// 64 x 64, or for the two large contractions the configuration in d.cfg
+// (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x64 on eight waves, 4: 64x64 with
+// two-way split K).
+template <int TAG, class TA, class TB, class TC, bool F32>
+static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
+  if (d.M <= 32 && d.N <= 32) return launch_cfg<1, 1, 4, 2, 2, TAG, TA, TB, TC, F32>(d, st);
+  if constexpr ((TAG == KC_POL_CONTRACT || TAG == KC_SE_CONTRACT) && !F32) {
+    switch (d.cfg) {
+      case 1: return launch_cfg<2, 2, 1, 2, 4, TAG, TA, TB, TC, F32>(d, st);
+      case 2: return launch_cfg<2, 2, 1, 4, 2, TAG, TA, TB, TC, F32>(d, st);
+      case 3: return launch_cfg<4, 2, 1, 2, 2, TAG, TA, TB, TC, F32>(d, st);
+      case 4: return launch_cfg<2, 2, 2, 2, 2, TAG, TA, TB, TC, F32>(d, st);
+      default: break;
+    }
+  }
+  if constexpr (TAG == KC_SE_CONTRACT && F32) return launch_cfg<2, 2, 1, 2, 4, TAG, TA, TB, TC, F32>(d, st);
+  return launch_cfg<2, 2, 1, 2, 2, TAG, TA, TB, TC, F32>(d, st);
 }
 
-// The two large contractions (M = naux, K or N = Nk nao^2) can take larger
-// tiles; cfg selects one (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x64 on
-// eight waves, 4: 64x64 with two-way split K).
+// Storage / precision combinations, only those each kernel class uses:
+// fp64 everywhere; in the mixed-precision path complex64 V and
+// intermediates with fp32 MFMA, and complex64 V read by the fp64 HF terms.
 template <int TAG>
-static hipError_t launch_big(const GemmDesc& d, hipStream_t st) {
-  switch (d.cfg) {
-    case 1: return launch_cfg<2, 2, 1, 2, 4, TAG>(d, st);
-    case 2: return launch_cfg<2, 2, 1, 4, 2, TAG>(d, st);
-    case 3: return launch_cfg<4, 2, 1, 2, 2, TAG>(d, st);
-    case 4: return launch_cfg<2, 2, 2, 2, 2, TAG>(d, st);
-    default: return launch_cfg<2, 2, 1, 2, 2, TAG>(d, st);
+static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
+  const int code = d.ta | (d.tb << 1) | (d.tc << 2) | (d.f32 << 3);
+  if (code == 0) return launch_typed<TAG, double2, double2, double2, false>(d, st);
+  if constexpr (TAG == KC_HF) {
+    if (code == 1) return launch_typed<TAG, float2, double2, double2, false>(d, st);
+    if (code == 2) return launch_typed<TAG, double2, float2, double2, false>(d, st);
   }
+  if constexpr (TAG == KC_POL_PRODUCER || TAG == KC_SE_PRODUCER) {
+    if (code == (8 | 1 | 2 | 4)) return launch_typed<TAG, float2, float2, float2, true>(d, st);
+  }
+  if constexpr (TAG == KC_POL_CONTRACT || TAG == KC_SE_FINAL) {
+    if (code == (8 | 1 | 2)) return launch_typed<TAG, float2, float2, double2, true>(d, st);
+  }
+  if constexpr (TAG == KC_SE_CONTRACT) {
+    if (code == (8 | 2 | 4)) return launch_typed<TAG, double2, float2, float2, true>(d, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.K <= 0) return hipErrorInvalidValue;
   switch (d.tag) {
-    case KC_POL_CONTRACT: return launch_big<KC_POL_CONTRACT>(d, st);
+    case KC_POL_CONTRACT: return launch_tag<KC_POL_CONTRACT>(d, st);
     case KC_POL_PRODUCER: return launch_tag<KC_POL_PRODUCER>(d, st);
-    case KC_SE_CONTRACT: return launch_big<KC_SE_CONTRACT>(d, st);
+    case KC_SE_CONTRACT: return launch_tag<KC_SE_CONTRACT>(d, st);
     case KC_SE_PRODUCER: return launch_tag<KC_SE_PRODUCER>(d, st);
     case KC_SE_FINAL: return launch_tag<KC_SE_FINAL>(d, st);
     case KC_TRANSFORM: return launch_tag<KC_TRANSFORM>(d, st);
@@ -716,5 +832,19 @@ __global__ void zero_int_k(int* p) { *p = 0; }
 
 hipError_t zero_flag_launch(int* p, hipStream_t st) {
   zero_int_k<<<1, 1, 0, st>>>(p);
+  return hipGetLastError();
+}
+
+// complex128 -> complex64 (rounding), n elements
+__global__ void __launch_bounds__(256) to_c64_k(const double2* x, float2* y, long long n) {
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride)
+    y[i] = float2{(float)x[i].x, (float)x[i].y};
+}
+
+hipError_t to_c64_launch(const double2* x, float2* y, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  to_c64_k<<<(unsigned)blocks, 256, 0, st>>>(x, y, n);
   return hipGetLastError();
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgw.so")
 
 GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPACE, GW_ERR_STATE = range(7)
 GW_FERMION, GW_BOSON = 0, 1
-GW_PREC_FP64 = 0
+GW_PREC_FP64, GW_PREC_FP32 = 0, 1
 GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF = range(4)
 KCLASS = dict(other=0, pol_contract=1, pol_producer=2, se_contract=3, se_producer=4,
               se_final=5, transform=6, hf=7, wdyson=8, dyson=9)
@@ -85,14 +85,15 @@ def load():
     return L
 
 
-def _ptr(t, name, shape=None):
+def _ptr(t, name, shape=None, dtype=None):
     import torch
     if t is None:
         return None
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{name} must be a CUDA tensor")
-    if t.dtype != torch.complex128:
-        raise TypeError(f"{name} must be complex128")
+    want = torch.complex128 if dtype is None else dtype
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {want}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -124,15 +125,20 @@ class Context:
     """One library context: dimensions, grids, stream and workspace."""
 
     def __init__(self, mesh, nao, naux, ntau, beta, ns=2, nF=None, nB=None, tau_chunk=None,
-                 max_nq=None, stream=None, workspace_gb=None):
+                 max_nq=None, stream=None, workspace_gb=None, precision="fp64"):
         import torch
         L = load()
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("precision is 'fp64' or 'fp32'")
+        self.precision = precision
+        self.v_dtype = torch.complex128 if precision == "fp64" else torch.complex64
         self.mesh = tuple(int(m) for m in mesh)
         self.nk = int(np.prod(self.mesh))
         self.nao, self.naux, self.ntau, self.beta, self.ns = int(nao), int(naux), int(ntau), float(beta), int(ns)
         self.nw_f, self.nw_b = self.ntau, self.ntau + 1
         d = Dims((ctypes.c_int * 3)(*self.mesh), self.nao, self.naux, self.ntau, self.nw_f,
-                 self.nw_b, self.ns, GW_PREC_FP64, self.beta)
+                 self.nw_b, self.ns, GW_PREC_FP64 if precision == "fp64" else GW_PREC_FP32,
+                 self.beta)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         st = L.gw_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
@@ -209,7 +215,8 @@ class Context:
 # --------------------------------------------------------------- the calls ---
 def gw_polarization(ctx, V, G_tau, q0, nq, P0_tau):
     ctx._check(load().gw_polarization(
-        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()), int(q0), int(nq),
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        int(q0), int(nq),
         _ptr(P0_tau, "P0_tau", (nq, ctx.ntau, ctx.naux, ctx.naux))), "gw_polarization")
 
 
@@ -255,7 +262,7 @@ def gw_screened_W(ctx, P0_iw, Pt_iw):
 
 def gw_self_energy(ctx, V, G_tau, Pt_tau, q0, nq, Sig_tau):
     ctx._check(load().gw_self_energy(
-        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
         _ptr(Pt_tau, "Pt_tau", (nq, ctx.ntau, ctx.naux, ctx.naux)), int(q0), int(nq),
         _ptr(Sig_tau, "Sig_tau", ctx.g_shape())), "gw_self_energy")
 
@@ -269,7 +276,8 @@ def gw_density(ctx, G_tau, S, gamma, want_count=True):
 
 
 def gw_hf(ctx, V, G_tau, gamma, Sig_inf):
-    ctx._check(load().gw_hf(ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+    ctx._check(load().gw_hf(ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype),
+                            _ptr(G_tau, "G_tau", ctx.g_shape()),
                             _ptr(gamma, "gamma", ctx.k_shape()) if gamma is not None else None,
                             _ptr(Sig_inf, "Sig_inf", ctx.k_shape())), "gw_hf")
 
