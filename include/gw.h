@@ -210,6 +210,50 @@ gw_status gw_find_mu(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig
 gw_status gw_mix(gw_ctx* ctx, long long n, double alpha, const gw_z* X_new, gw_z* Y,
                  double* maxdiff);
 
+/* ---- Derivatives of G -> (Sigma_inf, Sigma~) (GW_PREC_FP64 contexts) ----
+ * The map is holomorphic in G, so a vector-Jacobian product (VJP) applies the
+ * conjugate-transposed Jacobian to the cotangent; for a real loss L of the
+ * outputs this is the gradient dL/dRe + i dL/dIm (torch autograd convention).
+ * The forward quantities Pt (P~) are those of the same G.                   */
+
+/* Two-slot polarization: Eq. tilde_P0_tau with G_a in the tau slot
+ * (G^{k+q}(tau_i)) and G_b in the mirrored slot (G^k(tau_{ntau-1-i})).  The
+ * derivative of P0 along dG is P0[dG, G] + P0[G, dG].  accumulate = 1 adds to
+ * P0_tau instead of overwriting it.                                         */
+gw_status gw_polarization2(gw_ctx* ctx, const void* V, const gw_z* G_a, const gw_z* G_b, int q0,
+                           int nq, int accumulate, gw_z* P0_tau);
+
+/* Derivative of Eq. tilde_P_omega: since (I - P0)^{-1} = I + P~,
+ * d P~ = (I + P~) dP0 (I + P~).  adjoint = 0: Y = (I + Pt) X (I + Pt) (JVP);
+ * adjoint = 1: Y = (I + Pt)^H X (I + Pt)^H (VJP).  Arrays [q][m][Q][Q'] for
+ * nq * nw_b matrices; Y may not alias Pt or X.  Uses the GW_OP_SCREENED_W
+ * workspace.                                                                */
+gw_status gw_screened_W_lin(gw_ctx* ctx, const gw_z* Pt_iw, const gw_z* X_iw, int nq, int adjoint,
+                            gw_z* Y_iw);
+
+/* Adjoints of the transforms.  inverse = 0: X_tau[b][i][r] = sum_n
+ * conj(T[n][i]) X_iw[b][n][r] (VJP of gw_tau_to_iw); inverse = 1:
+ * X_iw[b][n][r] = sum_i conj(Tp[i][n]) X_tau[b][i][r] (VJP of gw_iw_to_tau).
+ * Xin / Xout are laid out as the cotangents of the output / input.          */
+gw_status gw_transform_adjoint(gw_ctx* ctx, int stat, int inverse, const gw_z* Xin,
+                               long long batch, long long R, gw_z* Xout);
+
+/* VJP of Eq. tilde_sigma2 for q = q0 .. q0+nq-1 with cotangent Sig_bar
+ * [tau][k][i][j]: G_bar += the G part (accumulated), Pt_bar[q-q0][tau]
+ * receives the P~ part (overwritten).                                        */
+gw_status gw_self_energy_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* Pt_tau,
+                             const gw_z* Sig_bar, int q0, int nq, gw_z* G_bar, gw_z* Pt_bar);
+
+/* VJP of Eq. tilde_P0_tau (both G slots) with cotangent P0_bar[q-q0][tau]:
+ * G_bar += (accumulated).                                                    */
+gw_status gw_polarization_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* P0_bar,
+                              int q0, int nq, gw_z* G_bar);
+
+/* VJP of G -> gamma = -G(beta^-) -> Sigma_inf = J + K (Eqs. HF_J, HF_K) with
+ * cotangent Sinf_bar [k][i][j]: G_bar += (accumulated).  The JVP is gw_hf
+ * itself, which is linear in G.                                             */
+gw_status gw_hf_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* Sinf_bar, gw_z* G_bar);
+
 /* Measurement.  While enabled, every launch of a kernel class is bracketed
  * by HIP events recorded on the context's stream; gw_profile_read
  * (synchronises) returns the launch count, the summed event time in ms and

@@ -532,12 +532,28 @@ static gw_status g_to_c64(gw_ctx* c, const gw_z* G, void** Gc) {
   return GW_OK;
 }
 
+static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Gb, int q0, int nq,
+                          gw_z* P0, bool accumulate);
+
 gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int nq, gw_z* P0) {
+  return pol_impl(c, V, G, G, q0, nq, P0, false);
+}
+
+gw_status gw_polarization2(gw_ctx* c, const void* V, const gw_z* Ga, const gw_z* Gb, int q0, int nq,
+                           int accumulate, gw_z* P0) {
+  if (c && c->d.precision != GW_PREC_FP64)
+    return fail(c, GW_ERR_ARG, "gw_polarization2 needs a GW_PREC_FP64 context");
+  return pol_impl(c, V, Ga, Gb, q0, nq, P0, accumulate != 0);
+}
+
+// G fills the tau slot (G^{k+q}(tau_i)), Gb the mirrored slot (G^k(tau_{ntau-1-i})).
+static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Gb, int q0, int nq,
+                          gw_z* P0, bool accumulate) {
   if (!c) return GW_ERR_ARG;
   if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
   if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
   if (nq == 0) return GW_OK;
-  if (!V || !G || !P0) return fail(c, GW_ERR_ARG, "NULL array");
+  if (!V || !G || !Gb || !P0) return fail(c, GW_ERR_ARG, "NULL array");
   const int tc = c->tc;
   if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_POLARIZATION, tc))
     return fail(c, GW_ERR_WORKSPACE, "polarization workspace too small");
@@ -550,11 +566,12 @@ gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int n
   char* Z = (char*)c->ws + align256((size_t)tc * S * ez);
   const char* Vd = (const char*)V;
   const char* Gd = (const char*)G;
+  const char* Gbd = (const char*)Gb;
   if (f32) {
     void* Gc = nullptr;
     gw_status s = g_to_c64(c, G, &Gc);
     if (s != GW_OK) return s;
-    Gd = (const char*)Gc;
+    Gd = Gbd = (const char*)Gc;
   }
   const int t = f32 ? 1 : 0;
   for (int q = q0; q < q0 + nq; ++q) {
@@ -576,7 +593,7 @@ gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int n
       if (s != GW_OK) return s;
       // Zt[tl][k][Q'][d][b] = sum_c G[nt-1-t0-tl][k][c][d] conj(V[q][k][Q'][c][b])
       g = gemm_desc();
-      g.A = Gd + (size_t)(nt - 1 - t0) * nk * n2 * ez; g.B = Aq; g.C = Z;
+      g.A = Gbd + (size_t)(nt - 1 - t0) * nk * n2 * ez; g.B = Aq; g.C = Z;
       g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
       g.am = two(nao, 1, -(long long)nk * n2); g.ak = aff(nao);
       g.bk = aff(nao); g.bn = two(nao, 1, n2); g.conjB = 1;
@@ -594,6 +611,7 @@ gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int n
       g.cm = aff(naux); g.cn = aff(1);
       g.ba = aff(S); g.bb = aff(S); g.bc = aff((long long)naux * naux);
       g.alpha_r = -(double)c->d.ns / nk;
+      if (accumulate) { g.beta_zero = 0; g.beta_r = 1.0; }
       g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = f32 ? kMixedChunk : 0;
       g.tag = KC_POL_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * naux * naux})) != GW_OK) return s;
@@ -893,6 +911,310 @@ gw_status gw_find_mu(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf,
       return s;
   }
   return GW_OK;
+}
+
+
+// =========================================================================
+// Derivatives of G -> (Sigma_inf, Sigma~).  The map is holomorphic in G, so
+// a vector-Jacobian product is the conjugate-transposed Jacobian applied to
+// the cotangent (the convention of torch autograd for complex tensors).
+// All of these need a GW_PREC_FP64 context.
+// =========================================================================
+
+static gw_status need_fp64(gw_ctx* c) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (c->d.precision != GW_PREC_FP64) return fail(c, GW_ERR_ARG, "derivatives need a GW_PREC_FP64 context");
+  return GW_OK;
+}
+
+gw_status gw_screened_W_lin(gw_ctx* c, const gw_z* Pt, const gw_z* X, int nq, int adjoint, gw_z* Y) {
+  gw_status s = need_fp64(c);
+  if (s != GW_OK) return s;
+  if (nq < 0 || nq > c->nk) return fail(c, GW_ERR_ARG, "nq out of range");
+  if (nq == 0) return GW_OK;
+  if (!Pt || !X || !Y) return fail(c, GW_ERR_ARG, "NULL array");
+  if (X == Y || Pt == Y) return fail(c, GW_ERR_ARG, "Y may not alias Pt or X");
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_SCREENED_W, nq))
+    return fail(c, GW_ERR_WORKSPACE, "screened_W workspace too small");
+  const int n = c->d.naux;
+  const long long nn = (long long)n * n, nmat = (long long)nq * c->d.nw_b;
+  double2* T = (double2*)c->ws;
+  // T = X + op(Pt) X, then Y = T + T op(Pt), op = identity (JVP) or ^H (VJP):
+  // (I + Pt) X (I + Pt) is the derivative of (I - P0)^{-1} P0 = (I - P0)^{-1} - I.
+  HIPCHK(c, mix_launch(nmat * nn, 1.0, (const double2*)X, T, nullptr, 2048, c->st));
+  GemmDesc g = gemm_desc();
+  g.A = Pt; g.B = X; g.C = T;
+  g.M = n; g.N = n; g.K = n; g.batch = (int)nmat;
+  if (adjoint) { g.am = aff(1); g.ak = aff(n); g.conjA = 1; } else { g.am = aff(n); g.ak = aff(1); }
+  g.bk = aff(n); g.bn = aff(1); g.cm = aff(n); g.cn = aff(1);
+  g.ba = g.bb = g.bc = aff(nn);
+  g.beta_zero = 0; g.beta_r = 1.0;
+  g.tag = KC_OTHER;
+  if ((s = run(c, g, Ext{0, nmat * nn}, Ext{0, nmat * nn}, Ext{0, nmat * nn})) != GW_OK) return s;
+  HIPCHK(c, mix_launch(nmat * nn, 1.0, T, (double2*)Y, nullptr, 2048, c->st));
+  g = gemm_desc();
+  g.A = T; g.B = Pt; g.C = Y;
+  g.M = n; g.N = n; g.K = n; g.batch = (int)nmat;
+  g.am = aff(n); g.ak = aff(1);
+  if (adjoint) { g.bk = aff(1); g.bn = aff(n); g.conjB = 1; } else { g.bk = aff(n); g.bn = aff(1); }
+  g.cm = aff(n); g.cn = aff(1);
+  g.ba = g.bb = g.bc = aff(nn);
+  g.beta_zero = 0; g.beta_r = 1.0;
+  g.tag = KC_OTHER;
+  return run(c, g, Ext{0, nmat * nn}, Ext{0, nmat * nn}, Ext{0, nmat * nn});
+}
+
+gw_status gw_transform_adjoint(gw_ctx* c, int stat, int inverse, const gw_z* Xin, long long batch,
+                               long long R, gw_z* Xout) {
+  gw_status s = need_fp64(c);
+  if (s != GW_OK) return s;
+  if (stat != GW_FERMION && stat != GW_BOSON) return fail(c, GW_ERR_ARG, "stat must be 0 or 1");
+  if (batch < 0 || R < 0 || batch > 65535 || R > 0x7fffffffLL)
+    return fail(c, GW_ERR_ARG, "batch or R out of range");
+  if (batch == 0 || R == 0) return GW_OK;
+  if (!Xin || !Xout) return fail(c, GW_ERR_ARG, "NULL array");
+  const int nt = c->d.ntau;
+  const int nw = stat == GW_FERMION ? c->d.nw_f : c->d.nw_b;
+  // inverse = 0: Xout[b][i][r] = sum_n conj(T[n][i]) Xin[b][n][r]  (adjoint of tau -> i w)
+  // inverse = 1: Xout[b][n][r] = sum_i conj(Tp[i][n]) Xin[b][i][r] (adjoint of i w -> tau)
+  const int rows = inverse ? nw : nt, inner = inverse ? nt : nw;
+  GemmDesc g = gemm_desc();
+  g.A = inverse ? (stat == GW_FERMION ? c->dTFp : c->dTBp) : (stat == GW_FERMION ? c->dTF : c->dTB);
+  g.B = Xin; g.C = Xout;
+  g.M = rows; g.N = (int)R; g.K = inner; g.batch = (int)batch;
+  g.am = aff(1); g.ak = aff(rows); g.conjA = 1;
+  g.bk = aff(R); g.bn = aff(1); g.cm = aff(R); g.cn = aff(1);
+  g.ba = aff(0); g.bb = aff((long long)inner * R); g.bc = aff((long long)rows * R);
+  g.tag = KC_TRANSFORM;
+  return run(c, g, Ext{0, (long long)rows * inner}, Ext{0, batch * inner * R}, Ext{0, batch * rows * R});
+}
+
+gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt,
+                             const gw_z* Sbar, int q0, int nq, gw_z* Gbar, gw_z* Ptbar) {
+  gw_status s = need_fp64(c);
+  if (s != GW_OK) return s;
+  if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
+  if (nq == 0) return GW_OK;
+  if (!V || !G || !Pt || !Sbar || !Gbar || !Ptbar) return fail(c, GW_ERR_ARG, "NULL array");
+  const int tc = c->tc;
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_SELF_ENERGY, tc))
+    return fail(c, GW_ERR_WORKSPACE, "self-energy workspace too small");
+  const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
+  const long long n2 = c->n2, sv = c->sv, S = (long long)nk * sv;
+  double2* R0 = (double2*)c->ws;
+  double2* R1 = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
+  for (int q = q0; q < q0 + nq; ++q) {
+    const gw_z* Aq = V + (size_t)q * nk * sv;
+    for (int t0 = 0; t0 < nt; t0 += tc) {
+      const int tcur = std::min(tc, nt - t0);
+      const gw_z* Ptq = Pt + ((long long)(q - q0) * nt + t0) * naux * naux;
+      // R0 = Vt[tl][Q][kk][b][j] = sum_Q' Pt[Q][Q'] V[q][kk][Q'][b][j]
+      GemmDesc g = gemm_desc();
+      g.A = Ptq; g.B = Aq; g.C = R0;
+      g.M = naux; g.N = nk * (int)n2; g.K = naux; g.batch = tcur;
+      g.am = aff(naux); g.ak = aff(1); g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
+      g.cm = aff((long long)nk * n2); g.cn = aff(1);
+      g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
+      g.tag = KC_SE_CONTRACT;
+      if ((s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
+      // R1 = L'[tl][kk][Q][a][j] = sum_i V[q][kk][Q][a][i] Sbar[t][kk+q][i][j]
+      g = gemm_desc();
+      g.A = Aq; g.B = Sbar + (size_t)t0 * nk * n2; g.C = R1;
+      g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
+      g.am = aff(nao); g.ak = aff(1); g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
+      g.cm = aff(nao); g.cn = two(nao, 1, S);
+      g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
+      g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;
+      g.tag = KC_SE_PRODUCER;
+      if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
+      // Gbar[t][kk][a][b] += -(1/nk) sum_{Q,j} L'[tl][kk][Q][a][j] conj(Vt[tl][Q][kk][b][j])
+      g = gemm_desc();
+      g.A = R1; g.B = R0; g.C = Gbar + (size_t)t0 * nk * n2;
+      g.M = nao; g.N = nao; g.K = naux * nao; g.batch = tcur * nk;
+      g.am = aff(nao); g.ak = two(nao, 1, n2);
+      g.bk = two(nao, 1, (long long)nk * n2); g.bn = aff(nao); g.conjB = 1;
+      g.cm = aff(nao); g.cn = aff(1);
+      g.ba = two(nk, sv, S); g.bb = two(nk, n2, S); g.bc = two(nk, n2, (long long)nk * n2);
+      g.alpha_r = -1.0 / nk; g.beta_zero = 0; g.beta_r = 1.0;
+      g.tag = KC_SE_FINAL;
+      if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * nk * n2})) != GW_OK) return s;
+      // R0 = Y[tl][kk][Q'][a][j] = sum_b G[t][kk][a][b] V[q][kk][Q'][b][j]
+      g = gemm_desc();
+      g.A = G + (size_t)t0 * nk * n2; g.B = Aq; g.C = R0;
+      g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
+      g.am = two(nao, nao, (long long)nk * n2); g.ak = aff(1);
+      g.bk = aff(nao); g.bn = two(nao, 1, n2);
+      g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
+      g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
+      g.tag = KC_SE_PRODUCER;
+      if ((s = run(c, g, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
+      // Ptbar[q][t][Q][Q'] = -(1/nk) sum_{kk,a,j} L'[tl][kk][Q][a][j] conj(Y[tl][kk][Q'][a][j])
+      g = gemm_desc();
+      g.A = R1; g.B = R0; g.C = Ptbar + ((long long)(q - q0) * nt + t0) * naux * naux;
+      g.M = naux; g.N = naux; g.K = nk * (int)n2; g.batch = tcur;
+      g.am = aff(n2); g.ak = two((unsigned)n2, 1, sv);
+      g.bk = two((unsigned)n2, 1, sv); g.bn = aff(n2); g.conjB = 1;
+      g.cm = aff(naux); g.cn = aff(1);
+      g.ba = aff(S); g.bb = aff(S); g.bc = aff((long long)naux * naux);
+      g.alpha_r = -1.0 / nk;
+      g.tag = KC_POL_CONTRACT;
+      if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * naux * naux})) != GW_OK) return s;
+    }
+  }
+  return GW_OK;
+}
+
+gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* P0bar, int q0,
+                              int nq, gw_z* Gbar) {
+  gw_status s = need_fp64(c);
+  if (s != GW_OK) return s;
+  if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
+  if (nq == 0) return GW_OK;
+  if (!V || !G || !P0bar || !Gbar) return fail(c, GW_ERR_ARG, "NULL array");
+  const int tc = c->tc;
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_POLARIZATION, tc))
+    return fail(c, GW_ERR_WORKSPACE, "polarization workspace too small");
+  const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
+  const long long n2 = c->n2, sv = c->sv, S = (long long)nk * sv;
+  const double sc = -(double)c->d.ns / nk;
+  double2* R0 = (double2*)c->ws;
+  double2* R1 = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
+  for (int q = q0; q < q0 + nq; ++q) {
+    const gw_z* Aq = V + (size_t)q * nk * sv;
+    for (int t0 = 0; t0 < nt; t0 += tc) {
+      const int tcur = std::min(tc, nt - t0);
+      const gw_z* Pb = P0bar + ((long long)(q - q0) * nt + t0) * naux * naux;
+      // --- tau slot: Gbar[t][k+q] += sc sum_{Q,d} conj(V[q][k][Q][d][a]) U[Q][k][d][b]
+      // R1 = W[tl][k][Q'][d][b] = sum_c conj(G[nt-1-t][k][c][d]) V[q][k][Q'][c][b]
+      GemmDesc g = gemm_desc();
+      g.A = G + (size_t)(nt - 1 - t0) * nk * n2; g.B = Aq; g.C = R1;
+      g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
+      g.am = two(nao, 1, -(long long)nk * n2); g.ak = aff(nao); g.conjA = 1;
+      g.bk = aff(nao); g.bn = two(nao, 1, n2);
+      g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
+      g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
+      g.tag = KC_POL_PRODUCER;
+      if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tc * S})) != GW_OK) return s;
+      // R0 = U[tl][Q][k][e] = sum_Q' Pbar[Q][Q'] W[tl][k][Q'][e]
+      g = gemm_desc();
+      g.A = Pb; g.B = R1; g.C = R0;
+      g.M = naux; g.N = nk * (int)n2; g.K = naux; g.batch = tcur;
+      g.am = aff(naux); g.ak = aff(1); g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
+      g.cm = aff((long long)nk * n2); g.cn = aff(1);
+      g.ba = aff((long long)naux * naux); g.bb = aff(S); g.bc = aff(S);
+      g.tag = KC_SE_CONTRACT;
+      if ((s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
+      // Gbar[t0+tl][k+q][a][b] += sc sum_{Q,d} conj(V[q][k][Q][d][a]) U[tl][Q][k][d][b]
+      g = gemm_desc();
+      g.A = Aq; g.B = R0; g.C = Gbar + (size_t)t0 * nk * n2;
+      g.M = nao; g.N = nao; g.K = naux * nao; g.batch = tcur * nk;
+      g.am = aff(1); g.ak = two(nao, nao, n2); g.conjA = 1;
+      g.bk = two(nao, nao, (long long)nk * n2); g.bn = aff(1);
+      g.cm = aff(nao); g.cn = aff(1);
+      g.ba = two(nk, sv, 0); g.bb = two(nk, n2, S); g.bc = two(nk, 0, (long long)nk * n2);
+      g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
+      g.alpha_r = sc; g.beta_zero = 0; g.beta_r = 1.0;
+      g.tag = KC_SE_FINAL;
+      if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * nk * n2})) != GW_OK) return s;
+      // --- mirrored slot: Gbar[nt-1-t][k] += sc sum_{Q',b} V[q][k][Q'][c][b] T[Q'][k][d][b]
+      // R1 = X[tl][k][Q][d][b] = sum_a V[q][k][Q][d][a] G[t][k+q][a][b]
+      g = gemm_desc();
+      g.A = Aq; g.B = G + (size_t)t0 * nk * n2; g.C = R1;
+      g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
+      g.am = aff(nao); g.ak = aff(1); g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
+      g.cm = aff(nao); g.cn = two(nao, 1, S);
+      g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
+      g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;
+      g.tag = KC_POL_PRODUCER;
+      if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * S})) != GW_OK) return s;
+      // R0 = T[tl][Q'][k][e] = sum_Q Pbar[Q][Q'] conj(X[tl][k][Q][e])
+      g = gemm_desc();
+      g.A = Pb; g.B = R1; g.C = R0;
+      g.M = naux; g.N = nk * (int)n2; g.K = naux; g.batch = tcur;
+      g.am = aff(1); g.ak = aff(naux); g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv); g.conjB = 1;
+      g.cm = aff((long long)nk * n2); g.cn = aff(1);
+      g.ba = aff((long long)naux * naux); g.bb = aff(S); g.bc = aff(S);
+      g.tag = KC_SE_CONTRACT;
+      if ((s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
+      // Gbar[nt-1-t0-tl][k][c][d] += sc sum_{Q',b} V[q][k][Q'][c][b] T[tl][Q'][k][d][b]
+      g = gemm_desc();
+      g.A = Aq; g.B = R0; g.C = Gbar + (size_t)(nt - 1 - t0) * nk * n2;
+      g.M = nao; g.N = nao; g.K = naux * nao; g.batch = tcur * nk;
+      g.am = aff(nao); g.ak = two(nao, 1, n2);
+      g.bk = two(nao, 1, (long long)nk * n2); g.bn = aff(nao);
+      g.cm = aff(nao); g.cn = aff(1);
+      g.ba = two(nk, sv, 0); g.bb = two(nk, n2, S); g.bc = two(nk, n2, -(long long)nk * n2);
+      g.alpha_r = sc; g.beta_zero = 0; g.beta_r = 1.0;
+      g.tag = KC_SE_FINAL;
+      if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S}, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2})) != GW_OK) return s;
+    }
+  }
+  return GW_OK;
+}
+
+gw_status gw_hf_vjp(gw_ctx* c, const gw_z* V, const gw_z* Sbar, gw_z* Gbar) {
+  gw_status s = need_fp64(c);
+  if (s != GW_OK) return s;
+  if (!V || !Sbar || !Gbar) return fail(c, GW_ERR_ARG, "NULL array");
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_HF, 1))
+    return fail(c, GW_ERR_WORKSPACE, "HF workspace too small");
+  const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
+  const long long n2 = c->n2, sv = c->sv;
+  double2* T2 = (double2*)c->ws;
+  double2* gb = (double2*)((char*)c->ws + align256((size_t)nk * sv * 16));
+  double2* vb = (double2*)((char*)gb + align256((size_t)nk * n2 * 16));
+  // vbar[Q] = sum_{k,e} conj(V[0][k][Q][e]) Sbar[k][e]
+  GemmDesc g = gemm_desc();
+  g.A = V; g.B = Sbar; g.C = vb;
+  g.M = naux; g.N = 1; g.K = nk * (int)n2;
+  g.am = aff(n2); g.ak = two((unsigned)n2, 1, sv); g.conjA = 1;
+  g.bk = aff(1); g.bn = aff(0); g.cm = aff(1); g.cn = aff(0);
+  g.tag = KC_HF;
+  if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)naux})) != GW_OK) return s;
+  // gbar[k'][a][b] = (ns/nk) sum_Q conj(V[0][k'][Q][b][a]) vbar[Q]
+  g = gemm_desc();
+  g.A = vb; g.B = V; g.C = gb;
+  g.M = 1; g.N = nk * (int)n2; g.K = naux;
+  g.am = aff(0); g.ak = aff(1);
+  g.bk = aff(n2); g.bn = three(nao, nao, nao, 1, sv); g.conjB = 1;
+  g.cm = aff(0); g.cn = aff(1);
+  g.alpha_r = (double)c->d.ns / nk;
+  g.tag = KC_HF;
+  if ((s = run(c, g, Ext{0, (long long)naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
+  for (int q = 0; q < nk; ++q) {
+    const gw_z* Aq = V + (size_t)q * nk * sv;
+    // T2[k][Q][b][i] = sum_j V[q][k][Q][j][b] Sbar[k][i][j]
+    g = gemm_desc();
+    g.A = Aq; g.B = Sbar; g.C = T2;
+    g.M = naux * nao; g.N = nao; g.K = nao; g.batch = nk;
+    g.am = two(nao, 1, n2); g.ak = aff(nao); g.bk = aff(1); g.bn = aff(nao);
+    g.cm = aff(nao); g.cn = aff(1);
+    g.ba = aff(sv); g.bb = aff(n2); g.bc = aff(sv);
+    g.tag = KC_HF;
+    if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)nk * sv})) != GW_OK) return s;
+    // gbar[k+q][a][b] += -(1/nk) sum_{Q,i} conj(V[q][k][Q][i][a]) T2[k][Q][b][i]
+    g = gemm_desc();
+    g.A = Aq; g.B = T2; g.C = gb;
+    g.M = nao; g.N = nao; g.K = naux * nao; g.batch = nk;
+    g.am = aff(1); g.ak = two(nao, nao, n2); g.conjA = 1;
+    g.bk = two(nao, 1, n2); g.bn = aff(nao);
+    g.cm = aff(nao); g.cn = aff(1);
+    g.ba = aff(sv); g.bb = aff(sv); g.bc = aff(0);
+    g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
+    g.alpha_r = -1.0 / nk; g.beta_zero = 0; g.beta_r = 1.0;
+    g.tag = KC_HF;
+    if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
+  }
+  // Gbar[t] += -w_t gbar   (gamma = -sum_t w_t G(t), w real)
+  g = gemm_desc();
+  g.A = c->dw; g.B = gb; g.C = Gbar;
+  g.M = nt; g.N = nk * (int)n2; g.K = 1;
+  g.am = aff(1); g.ak = aff(0); g.bk = aff(0); g.bn = aff(1);
+  g.cm = aff((long long)nk * n2); g.cn = aff(1);
+  g.alpha_r = -1.0; g.beta_zero = 0; g.beta_r = 1.0;
+  g.tag = KC_HF;
+  return run(c, g, Ext{0, (long long)nt}, Ext{0, (long long)nk * n2}, Ext{0, (long long)nt * nk * n2});
 }
 
 }  // extern "C"

@@ -26,6 +26,8 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_set_workspace", "gw_polarization", "gw_tau_to_iw", "gw_iw_to_tau",
            "gw_screened_W", "gw_self_energy", "gw_density", "gw_hf", "gw_dyson_G",
            "gw_find_mu", "gw_mix", "gw_grids_host", "gw_profile_enable", "gw_profile_read",
+           "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
+           "gw_polarization_vjp", "gw_hf_vjp",
            "gw_synchronize", "gw_status_string", "gw_last_error"]
 
 
@@ -72,6 +74,12 @@ def load():
         "gw_synchronize": ([P], I),
         "gw_mix": ([P, LL, D, P, P, P], I),
         "gw_profile_enable": ([P, I], I),
+        "gw_polarization2": ([P, P, P, P, I, I, I, P], I),
+        "gw_screened_W_lin": ([P, P, P, I, I, P], I),
+        "gw_transform_adjoint": ([P, I, I, P, LL, LL, P], I),
+        "gw_self_energy_vjp": ([P, P, P, P, P, I, I, P, P], I),
+        "gw_polarization_vjp": ([P, P, P, P, I, I, P], I),
+        "gw_hf_vjp": ([P, P, P, P], I),
         "gw_profile_read": ([P, I, P, P, P], I),
         "gw_grids_host": ([D, I, P, P, P, P, P, P, P, P, P, P], I),
         "gw_status_string": ([I], ctypes.c_char_p),
@@ -318,3 +326,53 @@ def gw_profile_read(ctx, kclass):
     ctx._check(load().gw_profile_read(ctx.h, int(kclass), ctypes.byref(n), ctypes.byref(ms),
                                       ctypes.byref(fl)), "gw_profile_read")
     return n.value, ms.value, fl.value
+
+
+# ----------------------------------------------------------- derivatives ---
+def gw_polarization2(ctx, V, G_a, G_b, q0, nq, P0_tau, accumulate=False):
+    ctx._check(load().gw_polarization2(
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_a, "G_a", ctx.g_shape()),
+        _ptr(G_b, "G_b", ctx.g_shape()), int(q0), int(nq), 1 if accumulate else 0,
+        _ptr(P0_tau, "P0_tau", (nq, ctx.ntau, ctx.naux, ctx.naux))), "gw_polarization2")
+
+
+def gw_screened_W_lin(ctx, Pt_iw, X_iw, Y_iw, adjoint=False):
+    nq = int(Pt_iw.shape[0])
+    shp = (nq, ctx.nw_b, ctx.naux, ctx.naux)
+    ctx._check(load().gw_screened_W_lin(ctx.h, _ptr(Pt_iw, "Pt_iw", shp), _ptr(X_iw, "X_iw", shp), nq,
+                                        1 if adjoint else 0, _ptr(Y_iw, "Y_iw", shp)),
+               "gw_screened_W_lin")
+
+
+def gw_transform_adjoint(ctx, stat, inverse, X_in, X_out, batch=1):
+    """inverse=False: cotangent of gw_tau_to_iw's output [b][nw][..] -> its input [b][ntau][..];
+    inverse=True: cotangent of gw_iw_to_tau's output [b][ntau][..] -> input [b][nw][..]."""
+    nw = ctx.nw_f if stat == GW_FERMION else ctx.nw_b
+    nin, nout = (nw, ctx.ntau) if not inverse else (ctx.ntau, nw)
+    R = X_in.numel() // (batch * nin)
+    if X_in.numel() != batch * nin * R or X_out.numel() != batch * nout * R:
+        raise ValueError("adjoint transform shapes do not match")
+    ctx._check(load().gw_transform_adjoint(ctx.h, int(stat), 1 if inverse else 0, _ptr(X_in, "X_in"),
+                                           int(batch), int(R), _ptr(X_out, "X_out")),
+               "gw_transform_adjoint")
+
+
+def gw_self_energy_vjp(ctx, V, G_tau, Pt_tau, Sig_bar, q0, nq, G_bar, Pt_bar):
+    shp = (nq, ctx.ntau, ctx.naux, ctx.naux)
+    ctx._check(load().gw_self_energy_vjp(
+        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        _ptr(Pt_tau, "Pt_tau", shp), _ptr(Sig_bar, "Sig_bar", ctx.g_shape()), int(q0), int(nq),
+        _ptr(G_bar, "G_bar", ctx.g_shape()), _ptr(Pt_bar, "Pt_bar", shp)), "gw_self_energy_vjp")
+
+
+def gw_polarization_vjp(ctx, V, G_tau, P0_bar, q0, nq, G_bar):
+    ctx._check(load().gw_polarization_vjp(
+        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        _ptr(P0_bar, "P0_bar", (nq, ctx.ntau, ctx.naux, ctx.naux)), int(q0), int(nq),
+        _ptr(G_bar, "G_bar", ctx.g_shape())), "gw_polarization_vjp")
+
+
+def gw_hf_vjp(ctx, V, Sinf_bar, G_bar):
+    ctx._check(load().gw_hf_vjp(ctx.h, _ptr(V, "V", ctx.v_shape()),
+                                _ptr(Sinf_bar, "Sinf_bar", ctx.k_shape()),
+                                _ptr(G_bar, "G_bar", ctx.g_shape())), "gw_hf_vjp")

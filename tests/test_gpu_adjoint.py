@@ -1,0 +1,91 @@
+"""Hand-written derivatives of G -> (Sigma_inf, Sigma~) on the GPU against the
+oracle's autograd twin (reverse and forward mode), plus the dot-product
+identity <S_bar, J dG> = <J^H S_bar, dG> on the GPU alone and central
+finite differences of the GPU forward."""
+import numpy as np
+import pytest
+
+from paper_2206_07660_amd import inputs as inp
+from oracle import grids as og
+from oracle import gw as ogw
+from oracle import gw_torch as ogt
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NS = 2
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def case():
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.adjoint import SigmaDerivatives
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(mesh=(2, 2, 2), nao=6, naux=30, ntau=12, beta=8.0, seed=21)
+    g = og.Grids(wl.beta, wl.ntau)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    G = ogw.g0_tau(H0, S, 0.05, wl.beta, g.tau)
+    rng = np.random.default_rng(22)
+    dG = inp.random_hermitian_tau(rng, wl.ntau, wl.nk, wl.nao, 0.05)
+    Sb_inf = inp.circular_gaussian(rng, (wl.nk, wl.nao, wl.nao), 1.0)
+    Sb_tau = inp.circular_gaussian(rng, G.shape, 1.0)
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=5)
+    path = GWPath(ctx, dev(V), dev(H0), dev(S), wl.n_target)
+    der = SigmaDerivatives(path)
+    yield dict(wl=wl, g=g, V=V, G=G, dG=dG, Sb_inf=Sb_inf, Sb_tau=Sb_tau, der=der, ctx=ctx)
+    ctx.close()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_vjp_matches_oracle_autograd(case):
+    d = case
+    s_inf, s_tau, Pt_tau, Pt_iw = d["der"].forward(dev(d["G"]))
+    Gb = d["der"].vjp(dev(d["G"]), Pt_tau, Pt_iw, dev(d["Sb_inf"]), dev(d["Sb_tau"])).cpu().numpy()
+    ref = ogt.vjp(d["V"], d["G"], d["Sb_inf"], d["Sb_tau"], d["g"], d["wl"].mesh, NS)
+    print("vjp rel err", _rel(Gb, ref))
+    assert _rel(Gb, ref) < 1e-11
+
+
+def test_jvp_matches_oracle_autograd(case):
+    d = case
+    s_inf, s_tau, Pt_tau, Pt_iw = d["der"].forward(dev(d["G"]))
+    di, ds = d["der"].jvp(dev(d["G"]), Pt_tau, Pt_iw, dev(d["dG"]))
+    ri, rs = ogt.jvp(d["V"], d["G"], d["dG"], d["g"], d["wl"].mesh, NS)
+    print("jvp rel err", _rel(di.cpu().numpy(), ri), _rel(ds.cpu().numpy(), rs))
+    assert _rel(di.cpu().numpy(), ri) < 1e-11 and _rel(ds.cpu().numpy(), rs) < 1e-11
+
+
+def test_dot_product_and_fd_on_gpu(case):
+    d = case
+    G = dev(d["G"])
+    s_inf, s_tau, Pt_tau, Pt_iw = d["der"].forward(G)
+    di, ds = d["der"].jvp(G, Pt_tau, Pt_iw, dev(d["dG"]))
+    Gb = d["der"].vjp(G, Pt_tau, Pt_iw, dev(d["Sb_inf"]), dev(d["Sb_tau"]))
+    lhs = np.vdot(d["Sb_inf"].ravel(), di.cpu().numpy().ravel()) + \
+        np.vdot(d["Sb_tau"].ravel(), ds.cpu().numpy().ravel())
+    rhs = np.vdot(Gb.cpu().numpy().ravel(), d["dG"].ravel())
+    print("dot test", lhs, rhs)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    h = 1e-6
+    p_inf, p_tau, _, _ = d["der"].forward(G + h * dev(d["dG"]))
+    m_inf, m_tau, _, _ = d["der"].forward(G - h * dev(d["dG"]))
+    fd = ((p_tau - m_tau) / (2 * h)).cpu().numpy()
+    assert _rel(ds.cpu().numpy(), fd) < 1e-7
+
+
+def test_autograd_function(case):
+    from paper_2206_07660_amd.adjoint import SigmaFunction
+    d = case
+    G = dev(d["G"]).requires_grad_(True)
+    s_inf, s_tau = SigmaFunction.apply(G, d["der"])
+    loss = (torch.conj(dev(d["Sb_inf"])) * s_inf).sum().real + (torch.conj(dev(d["Sb_tau"])) * s_tau).sum().real
+    loss.backward()
+    ref = ogt.vjp(d["V"], d["G"], d["Sb_inf"], d["Sb_tau"], d["g"], d["wl"].mesh, NS)
+    assert _rel(G.grad.cpu().numpy(), ref) < 1e-11
