@@ -135,7 +135,8 @@ gw_status gw_grids_host(double beta, int ntau, const long long* nF, const long l
  * tau_chunk is read as nq.  gw_set_workspace hands over a device buffer
  * (caller-owned, >= 256-byte aligned) and the tau chunk to use; calls that
  * need more than that buffer return GW_ERR_WORKSPACE.                       */
-enum { GW_OP_POLARIZATION = 0, GW_OP_SELF_ENERGY = 1, GW_OP_SCREENED_W = 2, GW_OP_HF = 3 };
+enum { GW_OP_POLARIZATION = 0, GW_OP_SELF_ENERGY = 1, GW_OP_SCREENED_W = 2, GW_OP_HF = 3,
+       GW_OP_DYSON_JVP = 4 };
 size_t gw_workspace_bytes(const gw_ctx* ctx, int op, int tau_chunk);
 gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
 
@@ -253,6 +254,25 @@ gw_status gw_polarization_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, con
  * cotangent Sinf_bar [k][i][j]: G_bar += (accumulated).  The JVP is gw_hf
  * itself, which is linear in G.                                             */
 gw_status gw_hf_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* Sinf_bar, gw_z* G_bar);
+
+/* JVP of the Dyson step with the electron count held fixed (Eq. Dyson,
+ * Sec. IV.A): for G(i w) at the current mu and a change of the self-energy
+ * (dSinf [k][i][j] and dSig_iw [n][k][i][j], either may be NULL),
+ *   dG = G (dSinf + dSig(i w_n) - dmu S) G,
+ * where dmu makes the change of N_e = -(ns/Nk) sum Re(r_n tr[G S]) vanish
+ * (r = w Tp, the beta^- row of the fermionic fit); fixed_mu = 1 uses
+ * dmu = 0.  *dmu (host, may be NULL) receives it.  Synchronises.  Uses the
+ * GW_OP_DYSON_JVP workspace.                                                */
+gw_status gw_dyson_jvp(gw_ctx* ctx, const gw_z* S, const gw_z* G_iw, const gw_z* dSinf,
+                       const gw_z* dSig_iw, int fixed_mu, gw_z* dG_iw, double* dmu);
+
+/* Vector operations of the Newton-Krylov solver: Y = a X + b Y for complex
+ * a, b over n elements (X may be NULL; b = 0 does not read Y), and
+ * out[0] + i out[1] = sum_i conj(X_i) Y_i (fixed reduction order; out is a
+ * host array; synchronises).                                                */
+gw_status gw_axpby(gw_ctx* ctx, long long n, double a_re, double a_im, const gw_z* X, double b_re,
+                   double b_im, gw_z* Y);
+gw_status gw_dot(gw_ctx* ctx, long long n, const gw_z* X, const gw_z* Y, double* out);
 
 /* Measurement.  While enabled, every launch of a kernel class is bracketed
  * by HIP events recorded on the context's stream; gw_profile_read

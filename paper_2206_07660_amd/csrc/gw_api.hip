@@ -41,6 +41,7 @@ struct gw_ctx {
   int *dplus = nullptr, *dminus = nullptr;
   int* dflag = nullptr;
   double* dpart = nullptr;   // nw_f * nk partials, then the reduced scalar at [nw_f*nk]
+  double* dred = nullptr;    // 2 * 1024 partials + 2 results for gw_dot
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int tc = 0;
@@ -285,7 +286,8 @@ gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
       upload(c, &c->dminus, minus.data(), minus.size() * sizeof(int)) != GW_OK ||
       hipMalloc((void**)&c->dflag, sizeof(int)) != hipSuccess ||
       hipMemset(c->dflag, 0, sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&c->dpart, ((size_t)d->nw_f * c->nk + 8) * sizeof(double)) != hipSuccess) {
+      hipMalloc((void**)&c->dpart, ((size_t)d->nw_f * c->nk + 8) * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&c->dred, (2 * 1024 + 8) * sizeof(double)) != hipSuccess) {
     gw_destroy(c);
     return GW_ERR_DEVICE;
   }
@@ -301,7 +303,7 @@ gw_status gw_destroy(gw_ctx* c) {
       (void)hipEventDestroy(p.second);
     }
   void* ptrs[] = {c->dTF, c->dTFp, c->dTB, c->dTBp, c->dw, c->drrow, c->dwF,
-                  c->dplus, c->dminus, c->dflag, c->dpart};
+                  c->dplus, c->dminus, c->dflag, c->dpart, c->dred};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -426,6 +428,8 @@ size_t gw_workspace_bytes(const gw_ctx* c, int op, int tau_chunk) {
   if (!c) return 0;
   const size_t z = 16;
   switch (op) {
+    case GW_OP_DYSON_JVP:
+      return 2 * align256((size_t)c->d.nw_f * c->nk * c->n2 * z);
     case GW_OP_POLARIZATION:
     case GW_OP_SELF_ENERGY:
       if (tau_chunk < 1 || tau_chunk > c->d.ntau) return 0;
@@ -1215,6 +1219,94 @@ gw_status gw_hf_vjp(gw_ctx* c, const gw_z* V, const gw_z* Sbar, gw_z* Gbar) {
   g.alpha_r = -1.0; g.beta_zero = 0; g.beta_r = 1.0;
   g.tag = KC_HF;
   return run(c, g, Ext{0, (long long)nt}, Ext{0, (long long)nk * n2}, Ext{0, (long long)nt * nk * n2});
+}
+
+
+// ---------------------------------------------------------------- vectors
+gw_status gw_axpby(gw_ctx* c, long long n, double ar, double ai, const gw_z* X, double br, double bi,
+                   gw_z* Y) {
+  if (!c) return GW_ERR_ARG;
+  if (n < 0 || !Y) return fail(c, GW_ERR_ARG, "bad gw_axpby arguments");
+  HIPCHK(c, axpby_launch(n, ar, ai, (const double2*)X, br, bi, (double2*)Y, c->st));
+  return GW_OK;
+}
+
+gw_status gw_dot(gw_ctx* c, long long n, const gw_z* X, const gw_z* Y, double* out) {
+  if (!c) return GW_ERR_ARG;
+  if (n < 0 || !X || !Y || !out) return fail(c, GW_ERR_ARG, "bad gw_dot arguments");
+  if (n == 0) {
+    out[0] = out[1] = 0.0;
+    return GW_OK;
+  }
+  const int nblk = (int)std::min<long long>((n + 255) / 256, 1024);
+  HIPCHK(c, dot_launch(n, (const double2*)X, (const double2*)Y, c->dred, nblk, c->dred + 2 * 1024,
+                       c->st));
+  HIPCHK(c, hipMemcpyAsync(out, c->dred + 2 * 1024, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GW_OK;
+}
+
+// ---------------------------------------------------------------- Dyson JVP
+gw_status gw_dyson_jvp(gw_ctx* c, const gw_z* S, const gw_z* G_iw, const gw_z* dSinf,
+                       const gw_z* dSig_iw, int fixed_mu, gw_z* dG_iw, double* dmu) {
+  gw_status s = need_fp64(c);
+  if (s != GW_OK) return s;
+  if (!S || !G_iw || !dG_iw) return fail(c, GW_ERR_ARG, "NULL array");
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_DYSON_JVP, 1))
+    return fail(c, GW_ERR_WORKSPACE, "dyson_jvp workspace too small");
+  const int nk = c->nk, nao = c->d.nao, nw = c->d.nw_f;
+  const long long n2 = c->n2, tot = (long long)nw * nk * n2;
+  double2* T = (double2*)c->ws;
+  double2* P2 = (double2*)((char*)c->ws + align256((size_t)tot * 16));
+  const int nb = nw * nk;
+  // one product X Y over all (n, k); Y's batch offset is given by its map
+  auto prod = [&](const void* A, Map3 ba, const void* B, Map3 bb, void* C, bool acc) -> gw_status {
+    GemmDesc g = gemm_desc();
+    g.A = A; g.B = B; g.C = C;
+    g.M = nao; g.N = nao; g.K = nao; g.batch = nb;
+    g.am = aff(nao); g.ak = aff(1); g.bk = aff(nao); g.bn = aff(1);
+    g.cm = aff(nao); g.cn = aff(1);
+    g.ba = ba; g.bb = bb; g.bc = aff(n2);
+    if (acc) { g.beta_zero = 0; g.beta_r = 1.0; }
+    g.tag = KC_OTHER;
+    const long long eb = bb.sin == n2 ? tot : (long long)nk * n2;
+    return run(c, g, Ext{0, tot}, Ext{0, eb}, Ext{0, tot});
+  };
+  const Map3 per_nk = aff(n2);                  // batch b = n*nk + k -> b * n2
+  const Map3 per_k = two(nk, n2, 0);            // -> k * n2
+  // dG = G (dSinf + dSig(i w)) G - dmu G S G  (Eq. Dyson differentiated)
+  bool have = false;
+  if (dSig_iw) {
+    if ((s = prod(G_iw, per_nk, dSig_iw, per_nk, T, false)) != GW_OK) return s;
+    have = true;
+  }
+  if (dSinf) {
+    if ((s = prod(G_iw, per_nk, dSinf, per_k, T, have)) != GW_OK) return s;
+    have = true;
+  }
+  if (!have) HIPCHK(c, axpby_launch(tot, 0.0, 0.0, nullptr, 0.0, 0.0, T, c->st));
+  if ((s = prod(T, per_nk, G_iw, per_nk, dG_iw, false)) != GW_OK) return s;
+  double m = 0.0;
+  if (!fixed_mu) {
+    // dmu keeps N_e = -(ns/Nk) sum Re(r_n tr[G S]) fixed:
+    // dmu = sum Re(r_n tr[G dSig G S]) / sum Re(r_n tr[G S G S])
+    if ((s = prod(G_iw, per_nk, S, per_k, T, false)) != GW_OK) return s;
+    if ((s = prod(T, per_nk, G_iw, per_nk, P2, false)) != GW_OK) return s;
+    double t1 = 0.0, t2 = 0.0;
+    HIPCHK(c, wtrace_launch((const double2*)dG_iw, (const double2*)S, c->drrow, nao, nk, nw, c->dpart, c->st));
+    HIPCHK(c, sum_launch(c->dpart, nb, 1.0, c->dpart + nb, c->st));
+    HIPCHK(c, hipMemcpyAsync(&t1, c->dpart + nb, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, wtrace_launch(P2, (const double2*)S, c->drrow, nao, nk, nw, c->dpart, c->st));
+    HIPCHK(c, sum_launch(c->dpart, nb, 1.0, c->dpart + nb, c->st));
+    HIPCHK(c, hipMemcpyAsync(&t2, c->dpart + nb, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (!(t2 != 0.0)) return fail(c, GW_ERR_SINGULAR, "dyson_jvp: dN/dmu is zero");
+    m = t1 / t2;
+    HIPCHK(c, axpby_launch(tot, -m, 0.0, P2, 1.0, 0.0, (double2*)dG_iw, c->st));
+  }
+  if (dmu) *dmu = m;
+  return GW_OK;
 }
 
 }  // extern "C"

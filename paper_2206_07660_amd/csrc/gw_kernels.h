@@ -81,3 +81,9 @@ hipError_t mix_launch(long long n, double alpha, const double2* X, double2* Y, d
                       int nblk, hipStream_t st);
 hipError_t zero_flag_launch(int* p, hipStream_t st);
 hipError_t to_c64_launch(const double2* x, float2* y, long long n, hipStream_t st);
+hipError_t axpby_launch(long long n, double ar, double ai, const double2* X, double br, double bi,
+                        double2* Y, hipStream_t st);
+hipError_t dot_launch(long long n, const double2* X, const double2* Y, double* part, int nblk,
+                      double* out, hipStream_t st);
+hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, int nao, int nk, int nw,
+                         double* part, hipStream_t st);

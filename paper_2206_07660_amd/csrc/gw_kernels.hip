@@ -848,3 +848,114 @@ hipError_t to_c64_launch(const double2* x, float2* y, long long n, hipStream_t s
   to_c64_k<<<(unsigned)blocks, 256, 0, st>>>(x, y, n);
   return hipGetLastError();
 }
+
+// Y = a X + b Y (complex a, b); X may be null (Y = b Y); b = 0 does not read Y.
+__global__ void __launch_bounds__(256) axpby_k(long long n, double ar, double ai, const double2* X,
+                                                double br, double bi, double2* Y) {
+  const long long stride = (long long)gridDim.x * 256;
+  const bool rb = (br != 0.0 || bi != 0.0);
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
+    double2 v{0.0, 0.0};
+    if (X) {
+      const double2 x = X[i];
+      v.x = ar * x.x - ai * x.y;
+      v.y = ar * x.y + ai * x.x;
+    }
+    if (rb) {
+      const double2 y = Y[i];
+      v.x += br * y.x - bi * y.y;
+      v.y += br * y.y + bi * y.x;
+    }
+    Y[i] = v;
+  }
+}
+
+hipError_t axpby_launch(long long n, double ar, double ai, const double2* X, double br, double bi,
+                        double2* Y, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  axpby_k<<<(unsigned)blocks, 256, 0, st>>>(n, ar, ai, X, br, bi, Y);
+  return hipGetLastError();
+}
+
+// part[2*b], part[2*b+1] = partial sum over block b of conj(X_i) Y_i
+__global__ void __launch_bounds__(256) dot_k(long long n, const double2* X, const double2* Y,
+                                             double* part) {
+  __shared__ double sr[256], si[256];
+  double ar = 0.0, ai = 0.0;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += stride) {
+    const double2 x = X[i], y = Y[i];
+    ar += x.x * y.x + x.y * y.y;
+    ai += x.x * y.y - x.y * y.x;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sr[threadIdx.x] += sr[threadIdx.x + h];
+      si[threadIdx.x] += si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr[0];
+    part[2 * blockIdx.x + 1] = si[0];
+  }
+}
+
+// out[0..1] = sums of the nb interleaved partials, in block order
+__global__ void sum2_k(const double* part, int nb, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  out[0] = a;
+  out[1] = b;
+}
+
+hipError_t dot_launch(long long n, const double2* X, const double2* Y, double* part, int nblk,
+                      double* out, hipStream_t st) {
+  dot_k<<<nblk, 256, 0, st>>>(n, X, Y, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  sum2_k<<<1, 64, 0, st>>>(part, nblk, out);
+  return hipGetLastError();
+}
+
+// part[n*nk + k] = Re(r_n tr[P[n][k] S[k]])
+__global__ void __launch_bounds__(64) wtrace_k(const double2* P, const double2* S, const double2* r,
+                                               int nao, int nk, double* part) {
+  const int k = blockIdx.x % nk, iw = blockIdx.x / nk;
+  const size_t nn = (size_t)nao * nao;
+  const double2* p = P + ((size_t)iw * nk + k) * nn;
+  double tr = 0.0, ti = 0.0;
+  for (int e = threadIdx.x; e < (int)nn; e += 64) {
+    const int a = e / nao, b = e % nao;
+    const double2 x = p[e];
+    const double2 s = S[k * nn + (size_t)b * nao + a];
+    tr += x.x * s.x - x.y * s.y;
+    ti += x.x * s.y + x.y * s.x;
+  }
+  __shared__ double sr[64], si[64];
+  sr[threadIdx.x] = tr;
+  si[threadIdx.x] = ti;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sr[threadIdx.x] += sr[threadIdx.x + h];
+      si[threadIdx.x] += si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = r[iw].x * sr[0] - r[iw].y * si[0];
+}
+
+hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, int nao, int nk, int nw,
+                         double* part, hipStream_t st) {
+  wtrace_k<<<(unsigned)(nw * nk), 64, 0, st>>>(P, S, r, nao, nk, part);
+  return hipGetLastError();
+}

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libgw.so")
 GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPACE, GW_ERR_STATE = range(7)
 GW_FERMION, GW_BOSON = 0, 1
 GW_PREC_FP64, GW_PREC_FP32 = 0, 1
-GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF = range(4)
+GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF, GW_OP_DYSON_JVP = range(5)
 KCLASS = dict(other=0, pol_contract=1, pol_producer=2, se_contract=3, se_producer=4,
               se_final=5, transform=6, hf=7, wdyson=8, dyson=9)
 
@@ -27,7 +27,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_screened_W", "gw_self_energy", "gw_density", "gw_hf", "gw_dyson_G",
            "gw_find_mu", "gw_mix", "gw_grids_host", "gw_profile_enable", "gw_profile_read",
            "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
-           "gw_polarization_vjp", "gw_hf_vjp",
+           "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
            "gw_synchronize", "gw_status_string", "gw_last_error"]
 
 
@@ -80,6 +80,9 @@ def load():
         "gw_self_energy_vjp": ([P, P, P, P, P, I, I, P, P], I),
         "gw_polarization_vjp": ([P, P, P, P, I, I, P], I),
         "gw_hf_vjp": ([P, P, P, P], I),
+        "gw_dyson_jvp": ([P, P, P, P, P, I, P, P], I),
+        "gw_axpby": ([P, LL, D, D, P, D, D, P], I),
+        "gw_dot": ([P, LL, P, P, P], I),
         "gw_profile_read": ([P, I, P, P, P], I),
         "gw_grids_host": ([D, I, P, P, P, P, P, P, P, P, P, P], I),
         "gw_status_string": ([I], ctypes.c_char_p),
@@ -167,7 +170,8 @@ class Context:
         self.tau_chunk = int(tau_chunk)
         need = max(L.gw_workspace_bytes(self.h, GW_OP_POLARIZATION, self.tau_chunk),
                    L.gw_workspace_bytes(self.h, GW_OP_SCREENED_W, self.max_nq),
-                   L.gw_workspace_bytes(self.h, GW_OP_HF, 1))
+                   L.gw_workspace_bytes(self.h, GW_OP_HF, 1),
+                   L.gw_workspace_bytes(self.h, GW_OP_DYSON_JVP, 1))
         self.workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
@@ -376,3 +380,33 @@ def gw_hf_vjp(ctx, V, Sinf_bar, G_bar):
     ctx._check(load().gw_hf_vjp(ctx.h, _ptr(V, "V", ctx.v_shape()),
                                 _ptr(Sinf_bar, "Sinf_bar", ctx.k_shape()),
                                 _ptr(G_bar, "G_bar", ctx.g_shape())), "gw_hf_vjp")
+
+
+def gw_dyson_jvp(ctx, S, G_iw, dSinf, dSig_iw, dG_iw, fixed_mu=False):
+    dmu = ctypes.c_double()
+    ctx._check(load().gw_dyson_jvp(
+        ctx.h, _ptr(S, "S", ctx.k_shape()), _ptr(G_iw, "G_iw", ctx.giw_shape()),
+        _ptr(dSinf, "dSinf", ctx.k_shape()) if dSinf is not None else None,
+        _ptr(dSig_iw, "dSig_iw", ctx.giw_shape()) if dSig_iw is not None else None,
+        1 if fixed_mu else 0, _ptr(dG_iw, "dG_iw", ctx.giw_shape()), ctypes.byref(dmu)),
+        "gw_dyson_jvp")
+    return dmu.value
+
+
+def gw_axpby(ctx, a, X, b, Y):
+    """Y = a X + b Y (complex scalars a, b)."""
+    a, b = complex(a), complex(b)
+    if X is not None and X.numel() != Y.numel():
+        raise ValueError("gw_axpby sizes differ")
+    ctx._check(load().gw_axpby(ctx.h, int(Y.numel()), a.real, a.imag,
+                               _ptr(X, "X") if X is not None else None, b.real, b.imag,
+                               _ptr(Y, "Y")), "gw_axpby")
+
+
+def gw_dot(ctx, X, Y):
+    """sum conj(X) Y as a Python complex."""
+    if X.numel() != Y.numel():
+        raise ValueError("gw_dot sizes differ")
+    out = (ctypes.c_double * 2)()
+    ctx._check(load().gw_dot(ctx.h, int(X.numel()), _ptr(X, "X"), _ptr(Y, "Y"), out), "gw_dot")
+    return complex(out[0], out[1])

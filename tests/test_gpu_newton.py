@@ -1,0 +1,54 @@
+"""Newton-Krylov (GMRES) solve of the scGW self-consistency against the damped
+fixed point on the GPU and against the oracle's own damped fixed point."""
+import numpy as np
+import pytest
+
+from paper_2206_07660_amd import inputs as inp
+from oracle import grids as og
+from oracle import gw as ogw
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NS = 2
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def test_newton_krylov_reaches_the_fixed_point():
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.newton import NewtonKrylov
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(mesh=(2, 2, 1), nao=4, naux=12, ntau=12, beta=10.0, seed=31, n_target=4.0)
+    g = og.Grids(wl.beta, wl.ntau)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS)
+    path = GWPath(ctx, dev(V), dev(H0), dev(S), wl.n_target)
+    # damped fixed point to convergence
+    st = path.start(0.0)
+    n_fp = 0
+    while n_fp < 200:
+        path.step(st)
+        n_fp += 1
+        if st.dsig < 1e-11:
+            break
+    fp_inf, fp_tau = st.sig_inf.cpu().numpy(), st.sig_tau.cpu().numpy()
+    # Newton-Krylov from the state after two damped steps
+    st2 = path.start(0.0)
+    path.step(st2)
+    path.step(st2)
+    nk = NewtonKrylov(path, restart=20, gmres_rtol=1e-8)
+    x, F = nk.solve(st2.sig_inf, st2.sig_tau, st2.mu, tol=1e-11, max_steps=12, log=print)
+    nk_inf, nk_tau = nk.inf(x).cpu().numpy(), nk.tau(x).cpu().numpy()
+    d_inf, d_tau = np.abs(nk_inf - fp_inf).max(), np.abs(nk_tau - fp_tau).max()
+    print(f"fixed point: {n_fp} Sigma evaluations; Newton-Krylov: {nk.stats.newton_steps} steps, "
+          f"{nk.stats.evaluations} evaluations + {nk.stats.jvps} JVPs; |dSigma| {d_inf:.2e} {d_tau:.2e}")
+    assert nk.stats.residuals[-1] < 1e-11
+    assert d_inf < 1e-9 and d_tau < 1e-9
+    # the oracle's damped fixed point reaches the same self-energy
+    hist = ogw.scgw(H0, S, V, g, wl.mesh, NS, wl.n_target, n_fp)
+    assert np.abs(hist[-1][1] - nk_inf).max() < 1e-8
+    assert np.abs(hist[-1][2] - nk_tau).max() < 1e-8
+    ctx.close()
