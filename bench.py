@@ -17,7 +17,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -41,11 +40,8 @@ def contraction_flops(nk, nao, naux, ntau):
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("gw_kernels.hip", "gw_kernels.h", "gw_api.hip"):
-        with open(os.path.join(ROOT, "paper_2206_07660_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    from paper_2206_07660_amd.build import source_hash
+    return source_hash()
 
 
 def load_traffic(kclass_name):
@@ -144,6 +140,48 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
     return res
 
 
+def compare_solvers(path, wl, tol):
+    """Damped fixed point vs Newton-Krylov (GMRES(20)) from the same start to
+    max |Sigma[G(x)] - x| < tol; both on the fp64 path."""
+    import torch
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.newton import NewtonKrylov
+    flops = contraction_flops(wl.nk, wl.nao, wl.naux, wl.ntau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = path.start(0.0)
+    n_fp = 0
+    while n_fp < 300:
+        path.step(st)
+        n_fp += 1
+        log(f"[solvers] fixed point {n_fp}: dSigma {st.dsig:.3e}")
+        if st.dsig < tol:
+            break
+    torch.cuda.synchronize()
+    t_fp = time.perf_counter() - t0
+    fp_inf, fp_tau = st.sig_inf.clone(), st.sig_tau.clone()
+    t0 = time.perf_counter()
+    st2 = path.start(0.0)
+    for _ in range(2):
+        path.step(st2)
+    nk = NewtonKrylov(path, restart=20, gmres_rtol=1e-3)
+    x, F = nk.solve(st2.sig_inf, st2.sig_tau, st2.mu, tol=tol, max_steps=30, log=log)
+    torch.cuda.synchronize()
+    t_nk = time.perf_counter() - t0
+    d = max((nk.inf(x) - fp_inf).abs().max().item(), (nk.tau(x) - fp_tau).abs().max().item())
+    return {"metric": "scGW solve to equal residual: damped fixed point vs Newton-Krylov (fp64)",
+            "workload": wl.name, "tol_max_abs_residual_Ha": tol,
+            "fixed_point": {"iterations": n_fp, "sigma_evaluations": n_fp, "seconds": t_fp,
+                            "final_dsigma": st.dsig},
+            "newton_krylov": {"newton_steps": nk.stats.newton_steps,
+                              "sigma_evaluations": nk.stats.evaluations + 2,
+                              "jvps": nk.stats.jvps, "seconds": t_nk,
+                              "residuals": nk.stats.residuals},
+            "speedup_nk_over_fixed_point": t_fp / t_nk,
+            "max_abs_sigma_difference_Ha": d,
+            "gflop_per_sigma_evaluation": flops / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +192,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (fp32 MFMA) comparison")
+    ap.add_argument("--compare-solvers", action="store_true",
+                    help="instead of the step benchmark: damped fixed point vs Newton-Krylov "
+                         "to the same residual (default workload ad-3x3x3)")
+    ap.add_argument("--tol", type=float, default=1e-8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -169,6 +211,8 @@ def main():
     from paper_2206_07660_amd import inputs as inp
     from paper_2206_07660_amd.scgw import GWPath
 
+    if args.compare_solvers and args.workload == "si-4x4x4":
+        args.workload = "ad-3x3x3"
     wl = inp.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -189,6 +233,10 @@ def main():
     log(f"[bench] grids built, tau chunk {ctx.tau_chunk}, workspace "
         f"{ctx.workspace.numel() / 1e9:.1f} GB after {time.time() - t0:.1f} s")
     path = GWPath(ctx, V, H0, S, wl.n_target, alpha=0.5)
+    if args.compare_solvers:
+        print(json.dumps(compare_solvers(path, wl, args.tol)), flush=True)
+        ctx.close()
+        return
     st = path.start(0.0)
     log(f"[bench] G0: mu {st.mu:.6f} N_e {st.n_e:.12f}")
     for i in range(args.warmup):

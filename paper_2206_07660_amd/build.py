@@ -12,6 +12,16 @@ LIB = os.path.join(HERE, "libgw.so")
 SOURCES = ["gw_kernels.hip", "gw_api.hip", "grids.cpp"]
 
 
+def source_hash():
+    """sha256 of the kernel and ABI sources (names counter summaries to a build)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gw_kernels.hip", "gw_kernels.h", "gw_api.hip"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def hipcc():
     for p in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if p and os.path.exists(p):

@@ -674,10 +674,46 @@ gw_status gw_screened_W(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt) {
   hipEvent_t e0 = nullptr;
   gw_status s = prof_begin(c, KC_WDYSON, &e0);
   if (s != GW_OK) return s;
-  HIPCHK(c, wdyson_launch((const double2*)P0, (double2*)Pt, (double2*)c->ws, c->d.naux,
-                          (long long)nq * c->d.nw_b, c->dflag, c->st));
-  const double n = c->d.naux;
-  if ((s = prof_end(c, KC_WDYSON, e0, (32.0 / 3.0) * n * n * n * nq * c->d.nw_b)) != GW_OK) return s;
+  // Blocked right-looking LU with row pivoting inside each panel of kNb
+  // columns; the trailing updates of A and of the right-hand side and the
+  // blocked back substitution are batched GEMMs over all nq * nw_b matrices.
+  const int n = c->d.naux, kNb = 32;
+  const long long nmat = (long long)nq * c->d.nw_b, nn = (long long)n * n;
+  double2* Am = (double2*)c->ws;
+  double2* Bm = (double2*)Pt;
+  HIPCHK(c, wlu_launch(0, (const double2*)P0, Am, Bm, n, 0, kNb, nmat, c->dflag, c->st));
+  auto gemm = [&](double2* X, long long xo, double2* Y, long long yo, double2* Z, long long zo, int M,
+                  int N, int K) -> gw_status {
+    if (M <= 0 || N <= 0 || K <= 0) return GW_OK;
+    GemmDesc g = gemm_desc();
+    g.A = X + xo; g.B = Y + yo; g.C = Z + zo;
+    g.M = M; g.N = N; g.K = K; g.batch = (int)nmat;
+    g.am = aff(n); g.ak = aff(1); g.bk = aff(n); g.bn = aff(1); g.cm = aff(n); g.cn = aff(1);
+    g.ba = g.bb = g.bc = aff(nn);
+    g.alpha_r = -1.0; g.beta_zero = 0; g.beta_r = 1.0;
+    g.tag = KC_OTHER;                 // timed as part of the whole solve (KC_WDYSON)
+    const long long span = nmat * nn;
+    return run(c, g, Ext{-xo, span - xo}, Ext{-yo, span - yo}, Ext{-zo, span - zo});
+  };
+  for (int j0 = 0; j0 < n; j0 += kNb) {
+    const int j1 = std::min(j0 + kNb, n), w = j1 - j0, rest = n - j1;
+    HIPCHK(c, wlu_launch(1, nullptr, Am, Bm, n, j0, kNb, nmat, c->dflag, c->st));
+    HIPCHK(c, wlu_launch(2, nullptr, Am, Bm, n, j0, kNb, nmat, c->dflag, c->st));
+    // A22 -= L21 U12 ;  B2 -= L21 B1
+    if ((s = gemm(Am, (long long)j1 * n + j0, Am, (long long)j0 * n + j1, Am, (long long)j1 * n + j1,
+                  rest, rest, w)) != GW_OK) return s;
+    if ((s = gemm(Am, (long long)j1 * n + j0, Bm, (long long)j0 * n, Bm, (long long)j1 * n,
+                  rest, n, w)) != GW_OK) return s;
+  }
+  const int nblk = (n + kNb - 1) / kNb;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int j0 = b * kNb, w = std::min(kNb, n - j0);
+    HIPCHK(c, wlu_launch(3, nullptr, Am, Bm, n, j0, kNb, nmat, c->dflag, c->st));
+    // B[0:j0] -= U[0:j0, j0:j0+w] B[j0:j0+w]
+    if ((s = gemm(Am, (long long)j0, Bm, (long long)j0 * n, Bm, 0, j0, n, w)) != GW_OK) return s;
+  }
+  const double nd = n;
+  if ((s = prof_end(c, KC_WDYSON, e0, (32.0 / 3.0) * nd * nd * nd * nmat)) != GW_OK) return s;
   return read_flag(c, "screened_W");
 }
 
@@ -722,6 +758,7 @@ gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt
       g.cm = aff((long long)nk * n2); g.cn = aff(1);
       g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
       g.ta = 0; g.tb = g.tc = t; g.f32 = t;
+      g.batch_fastest = 1;                      // every tau reads the same V slab
       g.tag = KC_SE_CONTRACT;
       gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
       if (s != GW_OK) return s;
@@ -1020,6 +1057,7 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
       g.am = aff(naux); g.ak = aff(1); g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
       g.cm = aff((long long)nk * n2); g.cn = aff(1);
       g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
+      g.batch_fastest = 1;
       g.tag = KC_SE_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
       // R1 = L'[tl][kk][Q][a][j] = sum_i V[q][kk][Q][a][i] Sbar[t][kk+q][i][j]

@@ -43,6 +43,7 @@ struct GemmDesc {
   int ta, tb, tc;   // storage types of A, B, C (0 complex128, 1 complex64)
   int f32;          // 1: fp32 MFMA with fp64 promotion every kchunk K-elements
   int kchunk;
+  int batch_fastest;  // workgroup order: 0 tile-fastest, 1 batch-fastest
 };
 
 static inline GemmDesc gemm_desc() {
@@ -87,3 +88,5 @@ hipError_t dot_launch(long long n, const double2* X, const double2* Y, double* p
                       double* out, hipStream_t st);
 hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, int nao, int nk, int nw,
                          double* part, hipStream_t st);
+hipError_t wlu_launch(int which, const double2* P0, double2* A, double2* B, int n, int j0, int nb,
+                      long long nmat, int* flag, hipStream_t st);

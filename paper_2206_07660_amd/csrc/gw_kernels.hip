@@ -144,9 +144,12 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   const unsigned w = blockIdx.x;
   const unsigned xcd = w % 8u, slot = w / 8u, per = total / 8u, rem = total % 8u;
   const unsigned logical = xcd < rem ? xcd * (per + 1u) + slot : rem * (per + 1u) + (xcd - rem) * per + slot;
-  const unsigned tile = logical % tiles;
+  // batch_fastest: the batch shares an operand (e.g. one V slab for every
+  // tau), so consecutive ids walk the batch and keep that operand's tile in L2.
+  const unsigned nbatch = (unsigned)d.batch;
+  const unsigned tile = d.batch_fastest ? logical / nbatch : logical % tiles;
   const int tm = (int)(tile % (unsigned)tiles_m), tn = (int)(tile / (unsigned)tiles_m);
-  const unsigned bt = logical / tiles;
+  const unsigned bt = d.batch_fastest ? logical % nbatch : logical / tiles;
 
   const TA* A = (const TA*)d.A + batch_off(d.ba, d.tab, d.tmod, d.tsA, bt);
   const TB* B = (const TB*)d.B + batch_off(d.bb, d.tab, d.tmod, d.tsB, bt);
@@ -957,5 +960,161 @@ __global__ void __launch_bounds__(64) wtrace_k(const double2* P, const double2* 
 hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, int nao, int nk, int nw,
                          double* part, hipStream_t st) {
   wtrace_k<<<(unsigned)(nw * nk), 64, 0, st>>>(P, S, r, nao, nk, part);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Blocked LU pieces for (I - P0) X = P0 (one workgroup per matrix).
+// A = I - P0 and B = P0 are set up by wlu_init_k; for each panel of nb
+// columns, wlu_panel_k factors the panel with row pivoting (swapping whole
+// rows of A and B), wlu_trsm_lower_k applies the panel's unit-lower block to
+// the rows of the panel, and the trailing updates are GEMMs on the host side.
+// wlu_trsm_upper_k solves one diagonal block of U during back substitution.
+__global__ void __launch_bounds__(256) wlu_init_k(const double2* __restrict__ P0, double2* A,
+                                                   double2* B, int n) {
+  const size_t nn = (size_t)n * n;
+  const double2* P = P0 + blockIdx.x * nn;
+  double2* Am = A + blockIdx.x * nn;
+  double2* Bm = B + blockIdx.x * nn;
+  for (size_t e = threadIdx.x; e < nn; e += 256) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    const double2 p = P[e];
+    Am[e] = double2{(r == c ? 1.0 : 0.0) - p.x, -p.y};
+    Bm[e] = p;
+  }
+}
+
+__global__ void __launch_bounds__(256) wlu_panel_k(double2* A, double2* B, int n, int j0, int nb,
+                                                    int* flag) {
+  const size_t nn = (size_t)n * n;
+  double2* Am = A + blockIdx.x * nn;
+  double2* Bm = B + blockIdx.x * nn;
+  const int tid = threadIdx.x, nt = 256;
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  __shared__ double2 pinv_s;
+  const int j1 = min(j0 + nb, n);
+  for (int j = j0; j < j1; ++j) {
+    double best = -1.0;
+    int bi = j;
+    for (int r = j + tid; r < n; r += nt) {
+      const double2 a = Am[(size_t)r * n + j];
+      const double v = fabs(a.x) + fabs(a.y);
+      if (v > best) { best = v; bi = r; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double o = sv[tid + s];
+        const int oi = si[tid + s];
+        if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) { sv[tid] = o; si[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int p = si[0];
+    if (tid == 0 && !(sv[0] > 0.0)) atomicOr(flag, 1);
+    if (p != j) {
+      for (int c = tid; c < n; c += nt) {
+        double2 t = Am[(size_t)j * n + c];
+        Am[(size_t)j * n + c] = Am[(size_t)p * n + c];
+        Am[(size_t)p * n + c] = t;
+        t = Bm[(size_t)j * n + c];
+        Bm[(size_t)j * n + c] = Bm[(size_t)p * n + c];
+        Bm[(size_t)p * n + c] = t;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double2 a = Am[(size_t)j * n + j];
+      const double den = a.x * a.x + a.y * a.y;
+      pinv_s = den > 0.0 ? double2{a.x / den, -a.y / den} : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    const double2 pi = pinv_s;
+    for (int r = j + 1 + tid; r < n; r += nt) {
+      const double2 a = Am[(size_t)r * n + j];
+      Am[(size_t)r * n + j] = double2{a.x * pi.x - a.y * pi.y, a.x * pi.y + a.y * pi.x};
+    }
+    __syncthreads();
+    // rank-1 update of the rest of the panel
+    const int w = j1 - j - 1;
+    if (w > 0) {
+      const size_t cnt = (size_t)(n - j - 1) * w;
+      for (size_t e = tid; e < cnt; e += nt) {
+        const int r = j + 1 + (int)(e / w), c = j + 1 + (int)(e % w);
+        const double2 l = Am[(size_t)r * n + j];
+        const double2 u = Am[(size_t)j * n + c];
+        double2 a = Am[(size_t)r * n + c];
+        a.x -= l.x * u.x - l.y * u.y;
+        a.y -= l.x * u.y + l.y * u.x;
+        Am[(size_t)r * n + c] = a;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// rows j0+1 .. j0+nb-1: U12 and B rows of the panel <- L11^{-1} (unit lower)
+__global__ void __launch_bounds__(256) wlu_trsm_lower_k(double2* A, double2* B, int n, int j0, int nb) {
+  const size_t nn = (size_t)n * n;
+  double2* Am = A + blockIdx.x * nn;
+  double2* Bm = B + blockIdx.x * nn;
+  const int j1 = min(j0 + nb, n);
+  const int ca = n - j1;               // trailing columns of A
+  for (int r = j0 + 1; r < j1; ++r) {
+    for (int e = threadIdx.x; e < ca + n; e += 256) {
+      double2* M = e < ca ? Am : Bm;
+      const int c = e < ca ? j1 + e : e - ca;
+      double2 x = M[(size_t)r * n + c];
+      for (int i = j0; i < r; ++i) {
+        const double2 l = Am[(size_t)r * n + i];
+        const double2 u = M[(size_t)i * n + c];
+        x.x -= l.x * u.x - l.y * u.y;
+        x.y -= l.x * u.y + l.y * u.x;
+      }
+      M[(size_t)r * n + c] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// rows j0 .. j1-1 of B <- U11^{-1} B (upper, back substitution within the block)
+__global__ void __launch_bounds__(256) wlu_trsm_upper_k(const double2* A, double2* B, int n, int j0,
+                                                         int nb) {
+  const size_t nn = (size_t)n * n;
+  const double2* Am = A + blockIdx.x * nn;
+  double2* Bm = B + blockIdx.x * nn;
+  const int j1 = min(j0 + nb, n);
+  for (int r = j1 - 1; r >= j0; --r) {
+    const double2 d = Am[(size_t)r * n + r];
+    const double den = d.x * d.x + d.y * d.y;
+    const double2 di = den > 0.0 ? double2{d.x / den, -d.y / den} : double2{0.0, 0.0};
+    for (int c = threadIdx.x; c < n; c += 256) {
+      double2 x = Bm[(size_t)r * n + c];
+      for (int i = r + 1; i < j1; ++i) {
+        const double2 u = Am[(size_t)r * n + i];
+        const double2 y = Bm[(size_t)i * n + c];
+        x.x -= u.x * y.x - u.y * y.y;
+        x.y -= u.x * y.y + u.y * y.x;
+      }
+      Bm[(size_t)r * n + c] = double2{x.x * di.x - x.y * di.y, x.x * di.y + x.y * di.x};
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t wlu_launch(int which, const double2* P0, double2* A, double2* B, int n, int j0, int nb,
+                      long long nmat, int* flag, hipStream_t st) {
+  if (nmat <= 0) return hipSuccess;
+  const unsigned g = (unsigned)nmat;
+  switch (which) {
+    case 0: wlu_init_k<<<g, 256, 0, st>>>(P0, A, B, n); break;
+    case 1: wlu_panel_k<<<g, 256, 0, st>>>(A, B, n, j0, nb, flag); break;
+    case 2: wlu_trsm_lower_k<<<g, 256, 0, st>>>(A, B, n, j0, nb); break;
+    case 3: wlu_trsm_upper_k<<<g, 256, 0, st>>>(A, B, n, j0, nb); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
