@@ -148,6 +148,17 @@ gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
 gw_status gw_polarization(gw_ctx* ctx, const void* V, const gw_z* G_tau, int q0, int nq,
                           gw_z* P0_tau);   /* V: gw_z (GW_PREC_FP64) or gw_c (GW_PREC_FP32) */
 
+/* Hermitian mode of gw_polarization (off after gw_create).  With on != 0 the
+ * caller states that every G_tau passed to gw_polarization is Hermitian in
+ * its orbital indices at each tau and k (true of the Green's function of a
+ * Hermitian H0, S and Sigma) and that V obeys V^{k+q,k}(Q) = V^{k,k+q}(Q)^H
+ * (Eq. tilde_P0_tau's pair relation).  P0^q(tau) is then Hermitian: the
+ * trace of the bubble for (Q', Q) is the complex conjugate of the one for
+ * (Q, Q').  Only the output tiles on and above the diagonal are contracted
+ * and the rest is filled by conjugation.  Results for inputs that break
+ * either property are undefined in this mode.  gw_polarization2 ignores it. */
+gw_status gw_set_hermitian(gw_ctx* ctx, int on);
+
 /* Eqs. tau_to_iw / P0t_to_P0w: X_iw[b][n][r] = sum_i T[n][i] X_tau[b][i][r]
  * for b < batch, r < R, with T the fermionic (stat = GW_FERMION, nw = nw_f)
  * or bosonic (GW_BOSON, nw = nw_b) transform.  X_iw is overwritten.          */

@@ -29,6 +29,7 @@ struct gw_ctx {
   std::vector<int> plus;   // host copy of the k+q table
   bool check_bounds = false;
   int tile_cfg = -1;       // tile configuration of the large contractions (-1: default)
+  bool herm = false;       // gw_set_hermitian: G Hermitian, V pair-Hermitian
   // measurement: event pairs per kernel class while profiling is on
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KC_COUNT];
@@ -199,7 +200,9 @@ gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
   hipError_t e = zgemm_launch(gg, c->st);
   if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("zgemm: ") + hipGetErrorString(e));
   // algorithmic flops: 8 real flops per complex multiply-add
-  return prof_end(c, g.tag, e0, 8.0 * g.M * (double)g.N * g.K * g.batch);
+  // useful flops: with g.tri only the entries on and above the diagonal
+  const double outs = g.tri ? 0.5 * g.M * (g.M + 1.0) : (double)g.M * g.N;
+  return prof_end(c, g.tag, e0, 8.0 * outs * g.K * g.batch);
 }
 
 gw_status read_flag(gw_ctx* c, const char* what) {
@@ -539,6 +542,12 @@ static gw_status g_to_c64(gw_ctx* c, const gw_z* G, void** Gc) {
 static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Gb, int q0, int nq,
                           gw_z* P0, bool accumulate);
 
+gw_status gw_set_hermitian(gw_ctx* c, int on) {
+  if (!c) return GW_ERR_ARG;
+  c->herm = on != 0;
+  return GW_OK;
+}
+
 gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int nq, gw_z* P0) {
   return pol_impl(c, V, G, G, q0, nq, P0, false);
 }
@@ -578,6 +587,9 @@ static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* G
     Gd = Gbd = (const char*)Gc;
   }
   const int t = f32 ? 1 : 0;
+  // P0^q(tau) is Hermitian when G^k(tau) is and V^{k+q,k}(Q) = V^{k,k+q}(Q)^H:
+  // then only the tiles on and above the diagonal are contracted.
+  const bool herm = c->herm && G == Gb && !accumulate;
   for (int q = q0; q < q0 + nq; ++q) {
     const char* Aq = Vd + (size_t)q * nk * sv * ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {
@@ -618,7 +630,9 @@ static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* G
       if (accumulate) { g.beta_zero = 0; g.beta_r = 1.0; }
       g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = f32 ? kMixedChunk : 0;
       g.tag = KC_POL_CONTRACT;
+      g.tri = herm ? 1 : 0;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * naux * naux})) != GW_OK) return s;
+      if (herm) HIPCHK(c, herm_fill_launch((double2*)g.C, naux, tcur, c->st));
     }
   }
   return GW_OK;

@@ -2,19 +2,46 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+// Unsigned division by an invariant divisor d >= 1 as a multiply-high, an
+// add and two shifts (Granlund and Montgomery, PLDI 1994, Fig. 4.1):
+// l = ceil(log2 d), mul = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1),
+// s2 = max(l - 1, 0); then n / d = (t + ((n - t) >> s1)) >> s2 with
+// t = mulhi(n, mul), exact for every 32-bit n.
+struct Udiv {
+  unsigned d, mul, s1, s2;
+};
+
+static inline Udiv udiv_make(unsigned d) {
+  unsigned l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  const unsigned long long mul = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return Udiv{d, (unsigned)mul, l < 1 ? l : 1u, l > 1 ? l - 1 : 0u};
+}
+
+__host__ __device__ __forceinline__ unsigned udiv(unsigned n, const Udiv& u) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned t = __umulhi(n, u.mul);
+#else
+  const unsigned t = (unsigned)(((unsigned long long)n * u.mul) >> 32);
+#endif
+  return (t + ((n - t) >> u.s1)) >> u.s2;
+}
+
 // Index map i -> (i / (din*dmid)) * sout + ((i / din) % dmid) * smid + (i % din) * sin.
-// An affine map has din = dmid = 0x7fffffff... use aff() below.
+// An affine map has din = 0x7fffffff, dmid = 1 (aff() below).  qin and qmid
+// divide by din and dmid.
 struct Map3 {
   long long sout, smid, sin;
   unsigned din, dmid;
+  Udiv qin, qmid;
 };
 
-static inline Map3 aff(long long s) { return Map3{0, 0, s, 0x7fffffffu, 1u}; }
-static inline Map3 two(unsigned din, long long sin, long long sout) {
-  return Map3{sout, 0, sin, din, 1u};
-}
 static inline Map3 three(unsigned din, long long sin, unsigned dmid, long long smid, long long sout) {
-  return Map3{sout, smid, sin, din, dmid};
+  return Map3{sout, smid, sin, din, dmid, udiv_make(din), udiv_make(dmid)};
+}
+static inline Map3 aff(long long s) { return three(0x7fffffffu, s, 1u, 0, 0); }
+static inline Map3 two(unsigned din, long long sin, long long sout) {
+  return three(din, sin, 1u, 0, sout);
 }
 
 // C[b](m, n) = alpha * sum_k op(A)[b](m, k) * op(B)[b](k, n) + beta * C[b](m, n)
@@ -44,6 +71,10 @@ struct GemmDesc {
   int f32;          // 1: fp32 MFMA with fp64 promotion every kchunk K-elements
   int kchunk;
   int batch_fastest;  // workgroup order: 0 tile-fastest, 1 batch-fastest
+  int tri;            // 1: M == N and only the output tiles on or above the
+                      // diagonal are computed (Hermitian products)
+  // filled by the launcher: dividers of the workgroup-id decomposition
+  Udiv q_tiles_m, q_tiles, q_batch, q_tmod;
 };
 
 static inline GemmDesc gemm_desc() {
@@ -88,5 +119,8 @@ hipError_t dot_launch(long long n, const double2* X, const double2* Y, double* p
                       double* out, hipStream_t st);
 hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, int nao, int nk, int nw,
                          double* part, hipStream_t st);
+// P[b] for b < nmat (n x n, row-major): entries below the diagonal become the
+// conjugates of their mirror images above it.
+hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st);
 hipError_t wlu_launch(int which, const double2* P0, double2* A, double2* B, int n, int j0, int nb,
                       long long nmat, int* flag, hipStream_t st);

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gw_kernels.h"
 
@@ -17,10 +18,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ long long map3(const Map3& m, unsigned i) {
-  unsigned a = i % m.din;
-  unsigned r = i / m.din;
-  unsigned b = r % m.dmid;
-  unsigned c = r / m.dmid;
+  const unsigned r = udiv(i, m.qin);
+  const unsigned a = i - r * m.din;
+  const unsigned c = udiv(r, m.qmid);
+  const unsigned b = r - c * m.dmid;
   return (long long)c * m.sout + (long long)b * m.smid + (long long)a * m.sin;
 }
 
@@ -32,10 +33,10 @@ struct Ctr {
 
 __device__ __forceinline__ Ctr ctr_init(const Map3& m, unsigned i) {
   Ctr c;
-  c.a = i % m.din;
-  unsigned r = i / m.din;
-  c.b = r % m.dmid;
-  unsigned o = r / m.dmid;
+  const unsigned r = udiv(i, m.qin);
+  c.a = i - r * m.din;
+  const unsigned o = udiv(r, m.qmid);
+  c.b = r - o * m.dmid;
   c.off = (long long)o * m.sout + (long long)c.b * m.smid + (long long)c.a * m.sin;
   return c;
 }
@@ -69,10 +70,10 @@ __device__ __forceinline__ void ctr_step1(const Map3& m, Ctr& c, unsigned st) {
   c.off += w2 ? (m.sout - (long long)m.dmid * m.smid) : 0;
 }
 
-__device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, int tmod, long long ts,
+__device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, const Udiv& tmod, long long ts,
                                                unsigned b) {
   long long o = map3(m, b);
-  if (ts != 0) o += (long long)tab[b % (unsigned)tmod] * ts;
+  if (ts != 0) o += (long long)tab[b - udiv(b, tmod) * tmod.d] * ts;
   return o;
 }
 
@@ -107,6 +108,10 @@ template <> struct Mfma<false> {
   static __device__ __forceinline__ Acc run(S a, S b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // c - a b: the f64 MFMA reads its last control field as negate flags
+  static __device__ __forceinline__ Acc run_neg(S a, S b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
+  }
   template <class T> static __device__ __forceinline__ S2 cvt(T v) { return to_d2(v); }
   // output row of accumulator element r held by lane group g = lane / 16
   static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
@@ -118,11 +123,51 @@ template <> struct Mfma<true> {
   static __device__ __forceinline__ Acc run(S a, S b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ Acc run_neg(S a, S b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(-a, b, c, 0, 0, 0);
+  }
   template <class T> static __device__ __forceinline__ S2 cvt(T v) { return to_f2(v); }
   static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
 };
 
-template <int WM, int WN, int WK, int BM, int BN, int TAG, bool WRAP1, class TA, class TB, class TC,
+// Raw buffer loads (gfx9 descriptor format).  A lane whose byte offset is not
+// below the record count reads zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, 0x7fffffff, 0x00020000);
+}
+// (The loaded vector is reinterpreted as a whole: element-wise access of the
+// builtins' vector results is not reliable with this compiler.)
+struct Dd { double x, y; };
+struct Ff { float x, y; };
+template <class T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so);
+template <> __device__ __forceinline__ double2 buf_load<double2>(__amdgpu_buffer_rsrc_t r, unsigned vo,
+                                                                 unsigned so) {
+  const Dd v = __builtin_bit_cast(Dd, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+  double2 x;
+  x.x = v.x;
+  x.y = v.y;
+  return x;
+}
+template <> __device__ __forceinline__ float2 buf_load<float2>(__amdgpu_buffer_rsrc_t r, unsigned vo,
+                                                               unsigned so) {
+  const Ff v = __builtin_bit_cast(Ff, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+  float2 x;
+  x.x = v.x;
+  x.y = v.y;
+  return x;
+}
+// x or -x by a uniform sign mask (0 or the sign bit of the high word)
+__device__ __forceinline__ double flip(double x, unsigned m) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, x) ^ ((unsigned long long)m << 32));
+}
+__device__ __forceinline__ float flip(float x, unsigned m) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, x) ^ m);
+}
+
+// KM: K-loop form.  0 general index maps (any number of carries per step);
+// 1 at most one carry per digit and step; 2 "uniform" (see launch_cfg): the
+// K offset is a wave-uniform scalar and each lane keeps a constant offset.
+template <int WM, int WN, int WK, int BM, int BN, int TAG, int KM, class TA, class TB, class TC,
           bool F32>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   typedef Mfma<F32> MM;
@@ -139,7 +184,9 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   // logical ids, so that the tiles of one batch entry (which share operand
   // rows and columns) meet in the same L2.
   const int tiles_m = (d.M + TM - 1) / TM;
-  const unsigned tiles = (unsigned)tiles_m * (unsigned)((d.N + TN - 1) / TN);
+  // with d.tri, the tiles on or above the diagonal, row by row
+  const unsigned tiles = d.tri ? (unsigned)tiles_m * (unsigned)(tiles_m + 1) / 2u
+                               : (unsigned)tiles_m * (unsigned)((d.N + TN - 1) / TN);
   const unsigned total = gridDim.x;
   const unsigned w = blockIdx.x;
   const unsigned xcd = w % 8u, slot = w / 8u, per = total / 8u, rem = total % 8u;
@@ -147,13 +194,29 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   // batch_fastest: the batch shares an operand (e.g. one V slab for every
   // tau), so consecutive ids walk the batch and keep that operand's tile in L2.
   const unsigned nbatch = (unsigned)d.batch;
-  const unsigned tile = d.batch_fastest ? logical / nbatch : logical % tiles;
-  const int tm = (int)(tile % (unsigned)tiles_m), tn = (int)(tile / (unsigned)tiles_m);
-  const unsigned bt = d.batch_fastest ? logical % nbatch : logical / tiles;
+  const unsigned lq = udiv(logical, d.batch_fastest ? d.q_batch : d.q_tiles);
+  const unsigned lr = logical - lq * (d.batch_fastest ? nbatch : tiles);
+  const unsigned tile = d.batch_fastest ? lq : lr;
+  int tm, tn;
+  if (d.tri) {
+    unsigned t = tile, r = 0, len = (unsigned)tiles_m;
+    while (t >= len) {
+      t -= len;
+      ++r;
+      --len;
+    }
+    tm = (int)r;
+    tn = (int)(r + t);
+  } else {
+    const unsigned tn_ = udiv(tile, d.q_tiles_m);
+    tm = (int)(tile - tn_ * (unsigned)tiles_m);
+    tn = (int)tn_;
+  }
+  const unsigned bt = d.batch_fastest ? lr : lq;
 
-  const TA* A = (const TA*)d.A + batch_off(d.ba, d.tab, d.tmod, d.tsA, bt);
-  const TB* B = (const TB*)d.B + batch_off(d.bb, d.tab, d.tmod, d.tsB, bt);
-  TC* C = (TC*)d.C + batch_off(d.bc, d.tab, d.tmod, d.tsC, bt);
+  const TA* A = (const TA*)d.A + batch_off(d.ba, d.tab, d.q_tmod, d.tsA, bt);
+  const TB* B = (const TB*)d.B + batch_off(d.bb, d.tab, d.q_tmod, d.tsB, bt);
+  TC* C = (TC*)d.C + batch_off(d.bc, d.tab, d.q_tmod, d.tsC, bt);
 
   const int m0 = tm * TM + wm * BM * 16;
   const int n0 = tn * TN + wn * BN * 16;
@@ -261,7 +324,7 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
       }
   };
   auto step = [&](Ctr& ca, Ctr& cb) {
-    if constexpr (WRAP1) {
+    if constexpr (KM == 1) {
       ctr_step1(d.ak, ca, kstep);
       ctr_step1(d.bk, cb, kstep);
     } else {
@@ -276,23 +339,118 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   const unsigned kfirst = 4u * wk;
   const unsigned nsteps = kfirst < K ? (K - kfirst + kstep - 1) / kstep : 0u;
   const unsigned cper = F32 && d.kchunk > 0 ? (unsigned)d.kchunk / kstep : 0u;
-  unsigned k = kfirst + kl;                  // this lane's k for the step in buffer 0
-  Ctr ca = ctr_init(d.ak, k), cb = ctr_init(d.bk, k);
   S2 a0[BM], b0[BN], a1[BM], b1[BN];
-  load(a0, b0, ca, cb, k < K);
-  unsigned s = 0;
-  for (; s + 1 < nsteps; s += 2) {
-    step(ca, cb);
-    load(a1, b1, ca, cb, k + kstep < K);
-    mma(a0, b0);
-    if (cper && (s + 1) % cper == 0) promote();
-    step(ca, cb);
-    load(a0, b0, ca, cb, k + 2u * kstep < K);
-    mma(a1, b1);
-    if (cper && (s + 2) % cper == 0) promote();
-    k += 2u * kstep;
+  if constexpr (KM == 2) {
+    // The four k of a step lie in one aligned group of every K map, so the
+    // K offset is one scalar per operand (the buffer soffset) and a lane's
+    // byte offset (voffset) is fixed for the whole loop.  Rows past M or N,
+    // and k past K on the last step, get an offset past the record count and
+    // read zeros.  The complex product needs no VALU: the -ai bi term uses
+    // the MFMA's negate flag, conjugation is a sign-bit flip.
+    constexpr unsigned kOut = 0x80000000u;
+    const __amdgpu_buffer_rsrc_t ra = buf_rsrc(A), rb = buf_rsrc(B);
+    unsigned voa[BM], vob[BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+      const int m = m0 + i * 16 + r16;
+      voa[i] = m < d.M ? (unsigned)((map3(d.am, m) + (long long)kl * d.ak.sin) * (long long)sizeof(TA)) : kOut;
+    }
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      const int n = n0 + j * 16 + r16;
+      vob[j] = n < d.N ? (unsigned)((map3(d.bn, n) + (long long)kl * d.bk.sin) * (long long)sizeof(TB)) : kOut;
+    }
+    Ctr ua = ctr_init(d.ak, kfirst), ub = ctr_init(d.bk, kfirst);
+    const unsigned ma = d.conjA ? 0x80000000u : 0u, mb = d.conjB ? 0x80000000u : 0u;
+    auto ldf = [&](S2 (&a)[BM], S2 (&b)[BN]) {
+      const unsigned soa = (unsigned)(ua.off * (long long)sizeof(TA));
+      const unsigned sob = (unsigned)(ub.off * (long long)sizeof(TB));
+#pragma unroll
+      for (int i = 0; i < BM; ++i) a[i] = MM::cvt(buf_load<TA>(ra, voa[i], soa));
+#pragma unroll
+      for (int j = 0; j < BN; ++j) b[j] = MM::cvt(buf_load<TB>(rb, vob[j], sob));
+      ctr_step1(d.ak, ua, kstep);
+      ctr_step1(d.bk, ub, kstep);
+    };
+    auto mmf = [&](const S2 (&a)[BM], const S2 (&b)[BN]) {
+      S ar[BM], ai[BM], br[BN], bi[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        ar[i] = a[i].x;
+        ai[i] = flip(a[i].y, ma);
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        br[j] = b[j].x;
+        bi[j] = flip(b[j].y, mb);
+      }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          accR[i][j] = MM::run(ar[i], br[j], accR[i][j]);
+          accI[i][j] = MM::run(ar[i], bi[j], accI[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          accR[i][j] = MM::run_neg(ai[i], bi[j], accR[i][j]);
+          accI[i][j] = MM::run(ai[i], br[j], accI[i][j]);
+        }
+    };
+    auto pc = [&](unsigned st) {
+      if constexpr (F32) {
+        if (cper && (st + 1) % cper == 0) promote();
+      }
+    };
+    // steps whose four k are all below K
+    const unsigned nfull = kfirst + 4u <= K ? (K - kfirst - 4u) / kstep + 1u : 0u;
+    unsigned s = 0;
+    if (nfull) ldf(a0, b0);
+    for (; s + 2 <= nfull; s += 2) {
+      ldf(a1, b1);
+      mmf(a0, b0);
+      pc(s);
+      if (s + 2 < nfull) ldf(a0, b0);
+      mmf(a1, b1);
+      pc(s + 1);
+    }
+    if (s < nfull) {
+      mmf(a0, b0);
+      pc(s);
+      ++s;
+    }
+    if (s < nsteps) {
+      // last, partial step: lanes with k >= K read zeros
+      const unsigned k0 = kfirst + s * kstep;
+      const bool kv = k0 + (unsigned)kl < K;
+#pragma unroll
+      for (int i = 0; i < BM; ++i) voa[i] = kv ? voa[i] : kOut;
+#pragma unroll
+      for (int j = 0; j < BN; ++j) vob[j] = kv ? vob[j] : kOut;
+      ldf(a0, b0);
+      mmf(a0, b0);
+      pc(s);
+    }
+  } else {
+    unsigned k = kfirst + kl;                  // this lane's k for the step in buffer 0
+    Ctr ca = ctr_init(d.ak, k), cb = ctr_init(d.bk, k);
+    load(a0, b0, ca, cb, k < K);
+    unsigned s = 0;
+    for (; s + 1 < nsteps; s += 2) {
+      step(ca, cb);
+      load(a1, b1, ca, cb, k + kstep < K);
+      mma(a0, b0);
+      if (cper && (s + 1) % cper == 0) promote();
+      step(ca, cb);
+      load(a0, b0, ca, cb, k + 2u * kstep < K);
+      mma(a1, b1);
+      if (cper && (s + 2) % cper == 0) promote();
+      k += 2u * kstep;
+    }
+    if (s < nsteps) mma(a0, b0);
   }
-  if (s < nsteps) mma(a0, b0);
   promote();
 
   // lane-local result, fp64
@@ -347,49 +505,108 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
 
   // epilogue: lane holds column lane%16 of each 16 x 16 block and the rows
   // given by MM::row (f64 MFMA: lane/16 + 4r; f32 MFMA: 4 (lane/16) + r)
+  long long roff[BM][4];
+  bool rok[BM][4];
 #pragma unroll
-  for (int j = 0; j < BN; ++j) {
-    const int n = n0 + j * 16 + r16;
-    if (n >= d.N) continue;
-    const long long con = map3(d.cn, n);
+  for (int i = 0; i < BM; ++i)
 #pragma unroll
-    for (int i = 0; i < BM; ++i)
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + i * 16 + MM::row(kl, r);
+      rok[i][r] = m < d.M;
+      roff[i][r] = rok[i][r] ? map3(d.cm, m) : 0;
+    }
+  // PLAIN: alpha = 1 and beta = 0, the common case, without the scaling
+  auto store = [&](auto plain) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + i * 16 + MM::row(kl, r);
-        if (m >= d.M) continue;
-        const long long o = map3(d.cm, m) + con;
-        const double xr = outR[i][j][r], xi = outI[i][j][r];
-        double2 v;
-        v.x = d.alpha_r * xr - d.alpha_i * xi;
-        v.y = d.alpha_r * xi + d.alpha_i * xr;
-        if (!d.beta_zero) {
-          const double2 c = to_d2(C[o]);
-          v.x += d.beta_r * c.x - d.beta_i * c.y;
-          v.y += d.beta_r * c.y + d.beta_i * c.x;
+    for (int j = 0; j < BN; ++j) {
+      const int n = n0 + j * 16 + r16;
+      if (n >= d.N) continue;
+      const long long con = map3(d.cn, n);
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (!rok[i][r]) continue;
+          const long long o = roff[i][r] + con;
+          const double xr = outR[i][j][r], xi = outI[i][j][r];
+          double2 v;
+          if constexpr (decltype(plain)::value) {
+            v.x = xr;
+            v.y = xi;
+          } else {
+            v.x = d.alpha_r * xr - d.alpha_i * xi;
+            v.y = d.alpha_r * xi + d.alpha_i * xr;
+            if (!d.beta_zero) {
+              const double2 c = to_d2(C[o]);
+              v.x += d.beta_r * c.x - d.beta_i * c.y;
+              v.y += d.beta_r * c.y + d.beta_i * c.x;
+            }
+          }
+          C[o] = from_d2<TC>(v);
         }
-        C[o] = from_d2<TC>(v);
-      }
-  }
+    }
+  };
+  if (d.beta_zero && d.alpha_r == 1.0 && d.alpha_i == 0.0)
+    store(std::true_type{});
+  else
+    store(std::false_type{});
 }
 
 static bool one_carry(const Map3& m, unsigned st) {
   return m.din >= st && (unsigned long long)m.din * m.dmid >= st;
 }
 
+// Upper bound of map3(m, i) over 0 <= i < n for non-negative strides.
+static long long map_max(const Map3& m, long long n) {
+  if (n <= 0) return 0;
+  const unsigned long long last = (unsigned long long)(n - 1), da = m.din, dm = m.dmid;
+  const unsigned long long a = std::min(da - 1ull, last), b = std::min(dm - 1ull, last / da);
+  const unsigned long long c = last / (da * dm);
+  return (long long)c * m.sout + (long long)b * m.smid + (long long)a * m.sin;
+}
+
+static bool nonneg(const Map3& m) { return m.sout >= 0 && m.smid >= 0 && m.sin >= 0; }
+
+// The uniform K loop (KM = 2) needs: every K map either never wraps inside
+// [0, K) or wraps at multiples of 4 (then the four k of a step, which start
+// at a multiple of 4, share all digits but the last); non-negative row,
+// column and K strides; and lane offset + K offset below 2^31 bytes.
+static bool uniform_k(const GemmDesc& d, unsigned kstep, long long ea, long long eb) {
+  auto aligned = [&](const Map3& m) {
+    return (m.din >= (unsigned)d.K || m.din % 4u == 0u) && one_carry(m, kstep);
+  };
+  if (!aligned(d.ak) || !aligned(d.bk)) return false;
+  if (!nonneg(d.am) || !nonneg(d.ak) || !nonneg(d.bk) || !nonneg(d.bn)) return false;
+  const long long lim = 0x7fffffffLL;
+  const long long va = (map_max(d.am, d.M) + 3 * d.ak.sin) * ea, ka = map_max(d.ak, d.K) * ea;
+  const long long vb = (map_max(d.bn, d.N) + 3 * d.bk.sin) * eb, kb = map_max(d.bk, d.K) * eb;
+  return va + ka + ea <= lim && vb + kb + eb <= lim;
+}
+
 template <int WM, int WN, int WK, int BM, int BN, int TAG, class TA, class TB, class TC, bool F32>
-static hipError_t launch_cfg(const GemmDesc& d, hipStream_t st) {
+static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
-  const long long tiles = (long long)((d.M + TM - 1) / TM) * ((d.N + TN - 1) / TN);
+  const long long tm_ = (d0.M + TM - 1) / TM;
+  if (d0.tri && (d0.M != d0.N || TM != TN)) return hipErrorInvalidValue;
+  const long long tiles = d0.tri ? tm_ * (tm_ + 1) / 2 : tm_ * ((d0.N + TN - 1) / TN);
   if (tiles > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  if (tiles * (long long)d.batch > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (tiles * (long long)d0.batch > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (d0.tmod <= 0) return hipErrorInvalidValue;
+  GemmDesc d = d0;
+  d.q_tiles_m = udiv_make((unsigned)((d.M + TM - 1) / TM));
+  d.q_tiles = udiv_make((unsigned)tiles);
+  d.q_batch = udiv_make((unsigned)d.batch);
+  d.q_tmod = udiv_make((unsigned)d.tmod);
   dim3 grid((unsigned)(tiles * d.batch), 1, 1);
   const unsigned kstep = 4u * WK;
   if (F32 && d.kchunk > 0 && d.kchunk % kstep) return hipErrorInvalidValue;
-  if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
-    zgemm_k<WM, WN, WK, BM, BN, TAG, true, TA, TB, TC, F32><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+  constexpr int nt = 64 * WM * WN * WK;
+  if (uniform_k(d, kstep, sizeof(TA), sizeof(TB)))
+    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
+  else if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
+    zgemm_k<WM, WN, WK, BM, BN, TAG, 1, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
   else
-    zgemm_k<WM, WN, WK, BM, BN, TAG, false, TA, TB, TC, F32><<<grid, 64 * WM * WN * WK, 0, st>>>(d);
+    zgemm_k<WM, WN, WK, BM, BN, TAG, 0, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
   return hipGetLastError();
 }
 
@@ -449,6 +666,29 @@ hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
     case KC_HF: return launch_tag<KC_HF>(d, st);
     default: return launch_tag<0>(d, st);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Lower triangle from the upper one: P[b](r, c) = conj(P[b](c, r)) for r > c.
+// Grid: x over the n*n entries of a matrix, y over the matrices; threads on
+// or above the diagonal do nothing.
+__global__ void herm_fill_k(double2* P, int n) {
+  const unsigned nn = (unsigned)n * (unsigned)n;
+  const unsigned e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= nn) return;
+  const unsigned r = e / (unsigned)n, c = e - r * (unsigned)n;
+  if (r <= c) return;
+  double2* M = P + (size_t)blockIdx.y * nn;
+  const double2 v = M[(size_t)c * n + r];
+  M[e] = double2{v.x, -v.y};
+}
+
+hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st) {
+  if (n <= 0 || nmat <= 0) return hipSuccess;
+  if (nmat > 65535 || (long long)n * n > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const unsigned bx = (unsigned)(((long long)n * n + 255) / 256);
+  herm_fill_k<<<dim3(bx, (unsigned)nmat, 1), 256, 0, st>>>(P, n);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

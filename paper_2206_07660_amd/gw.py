@@ -28,7 +28,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_find_mu", "gw_mix", "gw_grids_host", "gw_profile_enable", "gw_profile_read",
            "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
-           "gw_synchronize", "gw_status_string", "gw_last_error"]
+           "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian"]
 
 
 class GwError(RuntimeError):
@@ -63,6 +63,7 @@ def load():
         "gw_workspace_bytes": ([P, I, I], SZ),
         "gw_set_workspace": ([P, P, SZ, I], I),
         "gw_polarization": ([P, P, P, I, I, P], I),
+        "gw_set_hermitian": ([P, I], I),
         "gw_tau_to_iw": ([P, I, P, LL, LL, P], I),
         "gw_iw_to_tau": ([P, I, P, LL, LL, P], I),
         "gw_screened_W": ([P, P, I, P], I),
@@ -225,6 +226,10 @@ class Context:
 
 
 # --------------------------------------------------------------- the calls ---
+def gw_set_hermitian(ctx, on):
+    ctx._check(load().gw_set_hermitian(ctx.h, 1 if on else 0), "gw_set_hermitian")
+
+
 def gw_polarization(ctx, V, G_tau, q0, nq, P0_tau):
     ctx._check(load().gw_polarization(
         ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),

@@ -29,8 +29,13 @@ class State:
 
 
 class GWPath:
-    def __init__(self, ctx: gw.Context, V, H0, S, n_target, alpha=0.5):
+    """hermitian: every G given to sigma() is Hermitian per (tau, k), as any
+    Green's function of Hermitian H0, S and Sigma is, and V has the pair
+    relation; gw_polarization then contracts only half of each P0 matrix."""
+
+    def __init__(self, ctx: gw.Context, V, H0, S, n_target, alpha=0.5, hermitian=True):
         self.ctx, self.V, self.H0, self.S = ctx, V, H0, S
+        gw.gw_set_hermitian(ctx, hermitian)
         self.n_target, self.alpha = float(n_target), float(alpha)
         c = ctx
         z = dict(dtype=torch.complex128, device="cuda")

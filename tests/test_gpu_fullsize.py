@@ -48,6 +48,25 @@ def test_polarization_sampled(big):
     assert np.abs(Pa - np.conj(np.swapaxes(Pa, -1, -2))).max() < 1e-13
 
 
+def test_polarization_sampled_hermitian_mode(big):
+    """The mode the scGW driver and bench.py run: only the tiles on and above
+    the diagonal are contracted, the rest is filled by conjugation."""
+    from paper_2206_07660_amd import gw
+    wl, c = big["wl"], big["ctx"]
+    P = torch.empty((1, wl.ntau, wl.naux, wl.naux), dtype=torch.complex128, device="cuda")
+    gw.gw_set_hermitian(c, True)
+    try:
+        gw.gw_polarization(c, big["V"], big["dG"], big["q"], 1, P)
+    finally:
+        gw.gw_set_hermitian(c, False)
+    taus = [0, 37, 99]
+    ref = ogw.polarization(big["Vh"], big["G"], wl.mesh, wl.ns, qs=[big["q"]], taus=taus)
+    got = P.cpu().numpy()[0, taus]
+    err = np.abs(got - ref[0]).max()
+    print("full-size P0 err (Hermitian mode)", err)
+    assert err < TOL
+
+
 def test_self_energy_sampled(big):
     from paper_2206_07660_amd import gw
     wl, c = big["wl"], big["ctx"]

@@ -68,6 +68,36 @@ def test_polarization(small):
     gw.gw_polarization(c, small["dV"], small["dG"], 0, 0, P3[:0])
 
 
+def test_polarization_hermitian_mode(small):
+    """gw_set_hermitian: upper tiles contracted, lower ones filled by
+    conjugation; same values as the oracle and the general mode (G here is
+    the Hermitian non-interacting G(tau))."""
+    from paper_2206_07660_amd import gw
+    c = small["ctx"]
+    P = torch.empty((c.nk, c.ntau, c.naux, c.naux), dtype=torch.complex128, device="cuda")
+    Pg = torch.empty_like(P)
+    gw.gw_polarization(c, small["dV"], small["dG"], 0, c.nk, Pg)
+    gw.gw_set_hermitian(c, True)
+    try:
+        P.fill_(float("nan"))
+        gw.gw_polarization(c, small["dV"], small["dG"], 0, c.nk, P)
+        # q sub-range in the same mode
+        P2 = torch.empty((3, c.ntau, c.naux, c.naux), dtype=torch.complex128, device="cuda")
+        gw.gw_polarization(c, small["dV"], small["dG"], 2, 3, P2)
+    finally:
+        gw.gw_set_hermitian(c, False)
+    ref = ogw.polarization(small["V"], small["G"], small["wl"].mesh, NS)
+    Ph = host(P)
+    assert np.isfinite(Ph).all()
+    assert np.abs(Ph - ref).max() < TOL
+    assert np.abs(Ph - host(Pg)).max() < 1e-13
+    # lower triangle is exactly the conjugate of the upper one
+    low = np.tril_indices(c.naux, -1)
+    PhT = np.conj(np.swapaxes(Ph, -1, -2))
+    assert np.array_equal(Ph[..., low[0], low[1]], PhT[..., low[0], low[1]])
+    assert torch.equal(P2, P[2:5])
+
+
 @pytest.mark.parametrize("stat", [0, 1])
 def test_transforms(small, stat):
     from paper_2206_07660_amd import gw

@@ -135,6 +135,8 @@ def test_bruteforce_general_nonhermitian_G():
     G = G + 0.05 * inp.circular_gaussian(rng, G.shape, 1.0)
     P0 = gw.polarization(V, G, wl.mesh, NS)
     assert np.abs(P0 - brute.polarization(V, G, wl.mesh, NS)).max() < 1e-15
+    # Hermiticity of P0 (test_invariants) comes from that of G: it is lost here
+    assert np.abs(P0 - np.conj(np.swapaxes(P0, -1, -2))).max() > 1e-6
     Pt = inp.circular_gaussian(rng, P0.shape, 0.1)
     assert np.abs(gw.self_energy(V, G, Pt, wl.mesh)
                   - brute.self_energy(V, G, Pt, wl.mesh)).max() < 1e-15
