@@ -11,8 +11,8 @@ Run the workload under two counter passes, then summarize:
 The workload is a plain device-to-device copy of a known size (calibration:
 the counters read in KiB per dispatch; the factor that makes them equal to
 the copy's 2 x N bytes is applied to every kernel) followed by one
-polarization call (one q) and one self-energy call at the si-4x4x4 shape,
-the launch configuration bench.py times.
+polarization call (one q, Hermitian mode) and one self-energy call at the
+si-4x4x4 shape, the launch configuration bench.py times.
 """
 from __future__ import annotations
 
@@ -42,6 +42,7 @@ def run():
     rng = np.random.default_rng(1)
     G = torch.from_numpy(inp.random_hermitian_tau(rng, wl.ntau, wl.nk, wl.nao, 0.1)).cuda()
     ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, max_nq=1)
+    gw.gw_set_hermitian(ctx, True)           # as in the scGW loop (G is Hermitian)
     P = torch.empty((1, wl.ntau, wl.naux, wl.naux), dtype=torch.complex128, device="cuda")
     gw.gw_polarization(ctx, V, G, 0, 1, P)
     S = torch.zeros((wl.ntau, wl.nk, wl.nao, wl.nao), dtype=torch.complex128, device="cuda")
