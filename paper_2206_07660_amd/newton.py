@@ -31,10 +31,10 @@ class NKStats:
 
 
 class NewtonKrylov:
-    def __init__(self, path, restart=20, gmres_rtol=1e-6, max_restarts=10):
+    def __init__(self, path, restart=20, gmres_rtol=1e-6, max_restarts=10, per_q=False):
         self.path = path
         self.ctx = path.ctx
-        self.der = SigmaDerivatives(path)
+        self.der = SigmaDerivatives(path, per_q=per_q)
         c = self.ctx
         self.n_inf = c.nk * c.nao * c.nao
         self.N = self.n_inf + c.ntau * self.n_inf

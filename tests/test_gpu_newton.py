@@ -47,6 +47,12 @@ def test_newton_krylov_reaches_the_fixed_point():
           f"{nk.stats.evaluations} evaluations + {nk.stats.jvps} JVPs; |dSigma| {d_inf:.2e} {d_tau:.2e}")
     assert nk.stats.residuals[-1] < 1e-11
     assert d_inf < 1e-9 and d_tau < 1e-9
+    # the same solve with P~ rebuilt per q inside every derivative call
+    nkq = NewtonKrylov(path, restart=20, gmres_rtol=1e-8, per_q=True)
+    xq, Fq = nkq.solve(st2.sig_inf, st2.sig_tau, st2.mu, tol=1e-11, max_steps=12, log=print)
+    assert nkq.stats.residuals[-1] < 1e-11
+    assert np.abs(nkq.inf(xq).cpu().numpy() - nk_inf).max() < 1e-10
+    assert np.abs(nkq.tau(xq).cpu().numpy() - nk_tau).max() < 1e-10
     # the oracle's damped fixed point reaches the same self-energy
     hist = ogw.scgw(H0, S, V, g, wl.mesh, NS, wl.n_target, n_fp)
     assert np.abs(hist[-1][1] - nk_inf).max() < 1e-8
