@@ -1,0 +1,73 @@
+"""Parity at the largest shape (5x5x5 mesh, nao 26, naux 300, ntau 120,
+beta 200): V complex128 (50.7 GB) for the fp64 path and complex64 (25.4 GB)
+for the mixed-precision path, all q-slabs allocated on the GPU, one filled.
+Outputs the oracle can compute one by one: P0^q(tau) for sampled tau (both
+precisions, the fp64 one in the Hermitian mode the scGW driver uses) and one
+q-slab's self-energy contribution for sampled tau."""
+import numpy as np
+import pytest
+
+from paper_2206_07660_amd import inputs as inp
+from oracle import gw as ogw
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+MIXED_REL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def large():
+    torch.cuda.empty_cache()
+    wl = inp.WORKLOADS["si-5x5x5"]
+    q = 7
+    slab = inp.make_V_slab(wl, q)
+    rng = np.random.default_rng([wl.seed, 77])
+    G = inp.random_hermitian_tau(rng, wl.ntau, wl.nk, wl.nao, 0.1)
+    Vh = np.zeros((wl.nk,) + slab.shape, np.complex128)        # pages of the empty slabs stay untouched
+    Vh[q] = slab
+    taus = [0, 61, 119]
+    P_ref = ogw.polarization(Vh, G, wl.mesh, wl.ns, qs=[q], taus=taus)[0]
+    Pt = inp.random_hermitian_tau(rng, wl.ntau, 1, wl.naux, 0.01)
+    Pt = np.ascontiguousarray(np.swapaxes(Pt, 0, 1))             # [1][tau][Q][Q']
+    staus = [5, 90]
+    S_ref = ogw.self_energy(Vh, G[staus], Pt[:, staus], wl.mesh, qs=[q])
+    yield dict(wl=wl, q=q, slab=slab, G=G, taus=taus, P_ref=P_ref, Pt=Pt, staus=staus, S_ref=S_ref)
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_shape_sampled(large, precision):
+    from paper_2206_07660_amd import gw
+    d, wl, q = large, large["wl"], large["q"]
+    vt = torch.complex128 if precision == "fp64" else torch.complex64
+    V = torch.zeros((wl.nk, wl.nk, wl.naux, wl.nao, wl.nao), dtype=vt, device="cuda")
+    V[q].copy_(torch.from_numpy(d["slab"]).to(vt))
+    dG = torch.from_numpy(d["G"]).cuda()
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, max_nq=1,
+                     precision=precision)
+    try:
+        print(precision, "tau chunk", ctx.tau_chunk, flush=True)
+        gw.gw_set_hermitian(ctx, precision == "fp64")
+        P = torch.empty((1, wl.ntau, wl.naux, wl.naux), dtype=torch.complex128, device="cuda")
+        gw.gw_polarization(ctx, V, dG, q, 1, P)
+        got = P.cpu().numpy()[0, d["taus"]]
+        scale = np.abs(d["P_ref"]).max()
+        err_p = np.abs(got - d["P_ref"]).max()
+        S = torch.zeros((wl.ntau, wl.nk, wl.nao, wl.nao), dtype=torch.complex128, device="cuda")
+        gw.gw_self_energy(ctx, V, dG, torch.from_numpy(d["Pt"]).cuda(), q, 1, S)
+        got_s = S.cpu().numpy()[d["staus"]]
+        s_scale = np.abs(d["S_ref"]).max()
+        err_s = np.abs(got_s - d["S_ref"]).max()
+        print(f"{precision}: P0 err {err_p:.2e} (scale {scale:.2e}), Sigma err {err_s:.2e} "
+              f"(scale {s_scale:.2e})")
+        assert scale > 1e-5 and s_scale > 1e-7
+        if precision == "fp64":
+            assert err_p < TOL64 and err_s < TOL64
+        else:
+            assert err_p < MIXED_REL * scale and err_s < MIXED_REL * s_scale
+    finally:
+        ctx.close()
+        del V
+        torch.cuda.empty_cache()
