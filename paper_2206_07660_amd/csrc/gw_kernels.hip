@@ -665,7 +665,11 @@ static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
       default: break;
     }
   }
-  if constexpr (TAG == KC_SE_CONTRACT && F32) return launch_cfg<2, 2, 1, 2, 4, TAG, TA, TB, TC, F32>(d, st);
+  // fp32 MFMA steps are half as long, so the two large contractions split K
+  // over two waves per output block (64 x 64, 8 waves): measured 19.2 vs
+  // 20.5 ms (polarization) and 22.6 vs 26.0 ms (self-energy) per q
+  if constexpr ((TAG == KC_POL_CONTRACT || TAG == KC_SE_CONTRACT) && F32)
+    return launch_cfg<2, 2, 2, 2, 2, TAG, TA, TB, TC, F32>(d, st);
   // the producers (K = nao): 64 x 128 tiles give each wave twice the MFMA work
   // per load latency (measured 12.6 vs 14.0 ms per polarization call at
   // si-4x4x4)
