@@ -758,43 +758,61 @@ gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt
     Gd = (const char*)Gc;
   }
   const int t = f32 ? 1 : 0;
+  const bool kmajor = f32;   // layouts of Vt and L (see the final contraction)
   for (int q = q0; q < q0 + nq; ++q) {
     const char* Aq = Vd + (size_t)q * nk * sv * ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {
       const int tcur = std::min(tc, nt - t0);
       // Vt[tl][Q][kk][b][j] = sum_Q' Pt[q][t0+tl][Q][Q'] V[q][kk][Q'][b][j]
+      // (fp64), or Vt[tl][kk][Q][b][j] (mixed): see the final contraction
       GemmDesc g = gemm_desc();
       g.A = (const double2*)Pt + ((long long)(q - q0) * nt + t0) * naux * naux;
       g.B = Aq; g.C = Vt;
       g.M = naux; g.N = nk * (int)n2; g.K = naux; g.batch = tcur;
       g.am = aff(naux); g.ak = aff(1);
       g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
-      g.cm = aff((long long)nk * n2); g.cn = aff(1);
+      if (kmajor) { g.cm = aff(n2); g.cn = two((unsigned)n2, 1, sv); }
+      else { g.cm = aff((long long)nk * n2); g.cn = aff(1); }
       g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
       g.ta = 0; g.tb = g.tc = t; g.f32 = t;
       g.batch_fastest = 1;                      // every tau reads the same V slab
       g.tag = KC_SE_CONTRACT;
       gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
       if (s != GW_OK) return s;
-      // L[tl][kk][Q][i][b] = sum_a conj(V[q][kk][Q][a][i]) G[t0+tl][kk][a][b]
+      // L[tl][kk][Q][i][b] (fp64) or L[tl][kk][i][Q][b] (mixed)
+      //   = sum_a conj(V[q][kk][Q][a][i]) G[t0+tl][kk][a][b]
       g = gemm_desc();
       g.A = Aq; g.B = Gd + (size_t)t0 * nk * n2 * ez; g.C = L;
       g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
       g.am = two(nao, 1, n2); g.ak = aff(nao); g.conjA = 1;
       g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
-      g.cm = aff(nao); g.cn = two(nao, 1, S);
+      g.cm = kmajor ? two(nao, (long long)naux * nao, nao) : aff(nao);
+      g.cn = two(nao, 1, S);
       g.ba = aff(sv); g.bb = aff(n2); g.bc = aff(sv);
       g.ta = g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_SE_PRODUCER;
       if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
-      // Sig[t0+tl][kk+q][i][j] += -(1/nk) sum_{Q,b} L[tl][kk][Q][i][b] Vt[tl][Q][kk][b][j]
+      // Sig[t0+tl][kk+q][i][j] += -(1/nk) sum_{Q,b} L(i, (Q, b)) Vt((Q, b), j)
+      // In the mixed layouts K = (Q, b) is contiguous in L and has stride nao
+      // in Vt, so the uniform-K loop applies (fp32 MFMA steps are short
+      // enough for the per-lane index carries of the other layout to show:
+      // 6.6 vs 8.8 ms per q); the fp64 contraction streams at the HBM read
+      // rate either way and is faster with its operands' k-points adjacent
+      // (7.3 vs 8.1 ms per q).
       g = gemm_desc();
       g.A = L; g.B = Vt; g.C = (double2*)Sig + (long long)t0 * nk * n2;
       g.M = nao; g.N = nao; g.K = naux * nao; g.batch = tcur * nk;
-      g.am = aff(nao); g.ak = two(nao, 1, n2);
-      g.bk = two(nao, nao, (long long)nk * n2); g.bn = aff(1);
+      if (kmajor) {
+        g.am = aff((long long)naux * nao); g.ak = aff(1);
+        g.bk = aff(nao); g.bn = aff(1);
+        g.bb = two(nk, sv, S);
+      } else {
+        g.am = aff(nao); g.ak = two(nao, 1, n2);
+        g.bk = two(nao, nao, (long long)nk * n2); g.bn = aff(1);
+        g.bb = two(nk, n2, S);
+      }
       g.cm = aff(nao); g.cn = aff(1);
-      g.ba = two(nk, sv, S); g.bb = two(nk, n2, S); g.bc = two(nk, 0, (long long)nk * n2);
+      g.ba = two(nk, sv, S); g.bc = two(nk, 0, (long long)nk * n2);
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
       g.alpha_r = -1.0 / nk;
       g.beta_zero = 0; g.beta_r = 1.0;
