@@ -39,6 +39,11 @@
  *   sized by gw_workspace_bytes.
  * Spin.  Spin-restricted: ns (1 or 2) multiplies the polarization, the
  *   Hartree term and the electron count; exchange and Sigma~ carry no spin sum.
+ * Environment (read by gw_create).  GW_DEBUG_BOUNDS=1 makes every call check
+ *   on the host, before launching, that each GEMM descriptor it builds stays
+ *   inside the extents of its operands (a failed check returns GW_ERR_ARG);
+ *   GW_TILE_CFG=0..4 forces the tile shape of the two large fp64 contractions
+ *   (measurement only; the Hermitian polarization needs a square shape: 0, 4).
  */
 #ifndef GW_H
 #define GW_H

@@ -285,3 +285,34 @@ def test_workspace_too_small(small):
     base = (c.workspace.data_ptr() + 255) & ~255
     need = c.workspace.numel() - 256
     assert L.gw_set_workspace(c.h, ctypes.c_void_p(base), need, c.tau_chunk) == gw.GW_OK
+
+
+def test_descriptor_bounds_whole_path(small, monkeypatch):
+    """With GW_DEBUG_BOUNDS=1 every GEMM descriptor of the forward chain (both
+    precisions, Hermitian mode on and off), the transforms and the derivative
+    calls is proven on the host to stay inside its operands; a failure would
+    surface as a GwError."""
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.adjoint import SigmaDerivatives
+    from paper_2206_07660_amd.scgw import GWPath
+    monkeypatch.setenv("GW_DEBUG_BOUNDS", "1")
+    wl = small["wl"]
+    for precision in ("fp64", "fp32"):
+        c = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=7,
+                       precision=precision)
+        try:
+            V = small["dV"] if precision == "fp64" else small["dV"].to(torch.complex64)
+            for herm in (False, True):
+                path = GWPath(c, V, small["dH0"], small["dS"], wl.n_target, hermitian=herm)
+                s_inf, s_tau = path.sigma(small["dG"])
+                assert torch.isfinite(s_tau).all()
+                if precision == "fp64":
+                    der = SigmaDerivatives(path)
+                    si, st, Pt, Pw = der.forward(small["dG"])
+                    der.jvp(small["dG"], Pt, Pw, small["dG"])
+                    der.vjp(small["dG"], Pt, Pw, si, st)
+            st = path.start(small["mu0"])
+            path.step(st)
+            torch.cuda.synchronize()
+        finally:
+            c.close()
