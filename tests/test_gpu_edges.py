@@ -1,0 +1,78 @@
+"""GPU parity on edge shapes: a single k-point, an odd mesh with odd nao (so
+nao^2 is not a multiple of 4 and the contractions take the general index-map
+loop instead of the uniform-K one), the largest nao the Dyson kernel takes
+(60), and a non-orthogonal overlap S.  Each runs one Sigma[G] + Pi evaluation
+(both polarization modes), the Dyson equation and the mu search against the
+oracle at the fp64 tolerance, and the mixed-precision evaluation against its
+bound."""
+import numpy as np
+import pytest
+
+from paper_2206_07660_amd import inputs as inp
+from oracle import grids as og
+from oracle import gw as ogw
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+NS = 2
+
+CASES = {
+    "gamma-only": dict(mesh=(1, 1, 1), nao=5, naux=17, ntau=10, beta=12.0, seed=41, n_target=4.0),
+    "odd-mesh-odd-nao": dict(mesh=(3, 1, 2), nao=7, naux=33, ntau=14, beta=15.0, seed=42,
+                             n_target=6.0, s_kind="random"),
+    "nao-60": dict(mesh=(1, 1, 2), nao=60, naux=9, ntau=6, beta=6.0, seed=43, n_target=30.0,
+                   sigma=0.02),
+}
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_edge_shape_chain(name):
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(name=name, **CASES[name])
+    g = og.Grids(wl.beta, wl.ntau)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    mu0 = 0.03
+    G = ogw.g0_tau(H0, S, mu0, wl.beta, g.tau)
+    r_inf, r_tau, _ = ogw.sigma_evaluation(V, G, g, wl.mesh, NS)
+    c = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=5)
+    try:
+        for herm in (False, True):
+            path = GWPath(c, dev(V), dev(H0), dev(S), wl.n_target, hermitian=herm)
+            sinf, stau = path.sigma(dev(G))
+            e1 = np.abs(sinf.cpu().numpy() - r_inf).max()
+            e2 = np.abs(stau.cpu().numpy() - r_tau).max()
+            print(f"{name} hermitian={herm}: Sigma_inf err {e1:.2e}, Sigma~ err {e2:.2e} "
+                  f"(scale {np.abs(r_tau).max():.2e})")
+            assert e1 < TOL and e2 < TOL and np.abs(r_tau).max() > 1e-8
+        # Dyson with this self-energy and the mu search
+        siw = ogw.to_iw(g.TF, r_tau)
+        Giw = torch.empty(c.giw_shape(), dtype=torch.complex128, device="cuda")
+        gw.gw_dyson_G(c, dev(H0), dev(S), dev(r_inf), dev(siw), 0.1, Giw)
+        ref = ogw.dyson(H0, S, r_inf, siw, 0.1, g.wF)
+        assert np.abs(Giw.cpu().numpy() - ref).max() < TOL
+        Gt = torch.empty(c.g_shape(), dtype=torch.complex128, device="cuda")
+        mu, n = gw.gw_find_mu(c, dev(H0), dev(S), dev(r_inf), dev(siw), wl.n_target, 0.0,
+                              G_iw=Giw, G_tau=Gt)
+        mu_r, Giw_r, n_r = ogw.find_mu(H0, S, r_inf, siw, wl.n_target, g, NS, 0.0)
+        assert abs(n - wl.n_target) <= 1e-9 and abs(mu - mu_r) < 1e-11
+        assert np.abs(Gt.cpu().numpy() - ogw.to_tau(g.TFp, Giw_r)).max() < TOL
+    finally:
+        c.close()
+    # mixed precision on the same shape
+    c32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=5,
+                     precision="fp32")
+    try:
+        path = GWPath(c32, dev(V.astype(np.complex64)), dev(H0), dev(S), wl.n_target)
+        sinf, stau = path.sigma(dev(G))
+        e = max(np.abs(sinf.cpu().numpy() - r_inf).max(), np.abs(stau.cpu().numpy() - r_tau).max())
+        print(f"{name} mixed: max |dSigma| {e:.2e}")
+        assert e < 1e-6
+    finally:
+        c32.close()
