@@ -248,3 +248,67 @@ def test_fixed_point_independent_of_start():
     assert np.abs(stau - h1[-1][2]).max() < 1e-8
     assert np.abs(sinf - h1[-1][1]).max() < 1e-8
     assert np.abs(h1[-1][2] - h1[-2][2]).max() < 1e-8
+
+
+# ------------------------------------------------------------- Lindhard -----
+def test_lindhard_bubble_in_eigenbases():
+    """Non-interacting bubble on the bosonic grid against its closed form: in
+    the eigenbases of H0, P0^q(i Omega_m) = -(ns/Nk) sum_k sum_{a in k+q,
+    b in k} Vt(Q)_{ba} Vt'(Q')_{ab} (f_a - f_b) / (i Omega_m - xi_a + xi_b),
+    with beta f (1 - f) (the limit of the fraction) where xi_a = xi_b and
+    Omega_m = 0.  Pins Eq. tilde_P0_tau (with reading R1) and the bosonic
+    transform together; the only error is the tau-grid representation."""
+    wl = inp.small_workload(mesh=(2, 1, 1), nao=3, naux=4, ntau=40, beta=6.0, seed=17)
+    g = og.Grids(wl.beta, wl.ntau)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    mu = 0.1
+    G = gw.g0_tau(H0, S, mu, wl.beta, g.tau)
+    P0w = gw.to_iw(g.TB, np.moveaxis(gw.polarization(V, G, wl.mesh, NS), 1, 0))  # [m][q][Q][Q']
+    plus, _ = gw.mesh_tables(wl.mesh)
+    eig = [np.linalg.eigh(H0[k]) for k in range(wl.nk)]
+    ref = np.zeros_like(P0w)
+    for q in range(wl.nk):
+        for k in range(wl.nk):
+            kq = plus[q, k]
+            eb, Ub = eig[k]
+            ea, Ua = eig[kq]
+            xb, xa = eb - mu, ea - mu
+            fb, fa = 1 / (1 + np.exp(wl.beta * xb)), 1 / (1 + np.exp(wl.beta * xa))
+            Vt = np.einsum("bi,Qij,ja->Qba", Ub.conj().T, V[q, k], Ua)          # V^{k,k+q}(Q) in eigenbases
+            Vtp = np.conj(np.swapaxes(Vt, 1, 2))                                # V^{k+q,k}(Q') = V^{k,k+q}(Q')^H
+            for m, Om in enumerate(g.wB):
+                d = 1j * Om - xa[None, :] + xb[:, None]                         # [b][a]
+                num = fa[None, :] - fb[:, None]
+                frac = np.where(np.abs(d) > 1e-12, num / np.where(np.abs(d) > 1e-12, d, 1.0),
+                                wl.beta * fa[None, :] * (1 - fa[None, :]))
+                ref[m, q] += -(NS / wl.nk) * np.einsum("Qba,Pab,ba->QP", Vt, Vtp, frac)
+    err = np.abs(P0w - ref).max()
+    print("Lindhard max err", err, "scale", np.abs(ref).max())
+    assert err < 1e-10 * max(1.0, np.abs(ref).max()) and np.abs(ref).max() > 1e-3
+
+
+# ----------------------------------------------------- two-pole Dyson -------
+@pytest.mark.parametrize("eps,s,c,mu", [(0.3, 0.2, 0.15, 0.1), (-0.4, -0.1, 0.3, 0.05)])
+def test_two_pole_dyson_and_fit(eps, s, c, mu):
+    """One orbital with Sigma_inf = s and Sigma~(i w) = c / (i w - xi), xi =
+    eps - mu: G(z) = (z - xi) / ((z - z+)(z - z-)) with z+- = xi + s/2 +-
+    sqrt(s^2/4 + c), so G(tau) = -sum_+- Z+- e^{-z tau} / (1 + e^{-beta z})
+    with Z+- = (z+- - xi) / (z+- - z-+).  Pins the Dyson solve on the sparse
+    Matsubara set and the least-squares fit back to tau."""
+    beta, ntau = 10.0, 40
+    g = og.Grids(beta, ntau)
+    xi = eps - mu
+    H0 = np.full((1, 1, 1), eps, complex)
+    S = np.ones((1, 1, 1), complex)
+    sinf = np.full((1, 1, 1), s, complex)
+    siw = (c / (1j * g.wF - xi)).reshape(-1, 1, 1, 1)
+    Giw = gw.dyson(H0, S, sinf, siw, mu, g.wF)
+    r = np.sqrt(s * s / 4 + c)
+    zp, zm = xi + s / 2 + r, xi + s / 2 - r
+    Zp, Zm = (zp - xi) / (zp - zm), (zm - xi) / (zm - zp)
+    ref_iw = Zp / (1j * g.wF - zp) + Zm / (1j * g.wF - zm)
+    assert np.abs(Giw[:, 0, 0, 0] - ref_iw).max() < 1e-14
+    Gt = gw.to_tau(g.TFp, Giw)[:, 0, 0, 0]
+    # fermi_tau(z) = -e^{-z tau} / (1 + e^{-beta z})
+    ref_t = Zp * gw.fermi_tau([zp], g.tau, beta)[:, 0] + Zm * gw.fermi_tau([zm], g.tau, beta)[:, 0]
+    assert np.abs(Gt - ref_t).max() < 1e-10
