@@ -290,6 +290,13 @@ gw_status gw_axpby(gw_ctx* ctx, long long n, double a_re, double a_im, const gw_
                    double b_im, gw_z* Y);
 gw_status gw_dot(gw_ctx* ctx, long long n, const gw_z* X, const gw_z* Y, double* out);
 
+/* X[b] <- (X[b] + X[b]^H) / 2 for the nmat row-major n x n matrices of X
+ * (1 <= n <= 8192, nmat <= 65535 per call): the projection onto Hermitian
+ * matrices.  The self-energy of a Hermitian H0, S is Hermitian at every k
+ * and tau, and the chemical-potential constraint makes G(Sigma) only real-
+ * differentiable, so the Newton-Krylov iterates are kept on that subspace. */
+gw_status gw_hermitize(gw_ctx* ctx, gw_z* X, int n, long long nmat);
+
 /* Measurement.  While enabled, every launch of a kernel class is bracketed
  * by HIP events recorded on the context's stream; gw_profile_read
  * (synchronises) returns the launch count, the summed event time in ms and

@@ -1316,6 +1316,15 @@ gw_status gw_dot(gw_ctx* c, long long n, const gw_z* X, const gw_z* Y, double* o
   return GW_OK;
 }
 
+gw_status gw_hermitize(gw_ctx* c, gw_z* X, int n, long long nmat) {
+  if (!c) return GW_ERR_ARG;
+  if (n < 1 || n > 8192 || nmat < 0 || nmat > 65535) return fail(c, GW_ERR_ARG, "bad gw_hermitize sizes");
+  if (nmat == 0) return GW_OK;
+  if (!X) return fail(c, GW_ERR_ARG, "NULL array");
+  HIPCHK(c, herm_avg_launch((double2*)X, n, nmat, c->st));
+  return GW_OK;
+}
+
 // ---------------------------------------------------------------- Dyson JVP
 gw_status gw_dyson_jvp(gw_ctx* c, const gw_z* S, const gw_z* G_iw, const gw_z* dSinf,
                        const gw_z* dSig_iw, int fixed_mu, gw_z* dG_iw, double* dmu) {

@@ -122,5 +122,7 @@ hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, i
 // P[b] for b < nmat (n x n, row-major): entries below the diagonal become the
 // conjugates of their mirror images above it.
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st);
+// P[b] <- (P[b] + P[b]^H) / 2 for b < nmat (n x n, row-major).
+hipError_t herm_avg_launch(double2* P, int n, long long nmat, hipStream_t st);
 hipError_t wlu_launch(int which, const double2* P0, double2* A, double2* B, int n, int j0, int nb,
                       long long nmat, int* flag, hipStream_t st);

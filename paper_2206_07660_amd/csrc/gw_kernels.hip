@@ -731,6 +731,29 @@ __global__ void herm_fill_k(double2* P, int n) {
   M[e] = double2{v.x, -v.y};
 }
 
+// Hermitian part: one thread per entry (r, c) with r <= c of each matrix; it
+// reads both mirror entries and writes both.
+__global__ void herm_avg_k(double2* P, int n) {
+  const unsigned nn = (unsigned)n * (unsigned)n;
+  const unsigned e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= nn) return;
+  const unsigned r = e / (unsigned)n, c = e - r * (unsigned)n;
+  if (r > c) return;
+  double2* M = P + (size_t)blockIdx.y * nn;
+  const double2 a = M[e], b = M[(size_t)c * n + r];
+  const double2 v = double2{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+  M[e] = v;
+  M[(size_t)c * n + r] = double2{v.x, -v.y};
+}
+
+hipError_t herm_avg_launch(double2* P, int n, long long nmat, hipStream_t st) {
+  if (n <= 0 || nmat <= 0) return hipSuccess;
+  if (nmat > 65535 || (long long)n * n > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const unsigned bx = (unsigned)(((long long)n * n + 255) / 256);
+  herm_avg_k<<<dim3(bx, (unsigned)nmat, 1), 256, 0, st>>>(P, n);
+  return hipGetLastError();
+}
+
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st) {
   if (n <= 0 || nmat <= 0) return hipSuccess;
   if (nmat > 65535 || (long long)n * n > 0x7fffffffLL) return hipErrorInvalidConfiguration;

@@ -28,7 +28,8 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_find_mu", "gw_mix", "gw_grids_host", "gw_profile_enable", "gw_profile_read",
            "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
-           "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian"]
+           "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
+           "gw_hermitize"]
 
 
 class GwError(RuntimeError):
@@ -64,6 +65,7 @@ def load():
         "gw_set_workspace": ([P, P, SZ, I], I),
         "gw_polarization": ([P, P, P, I, I, P], I),
         "gw_set_hermitian": ([P, I], I),
+        "gw_hermitize": ([P, P, I, LL], I),
         "gw_tau_to_iw": ([P, I, P, LL, LL, P], I),
         "gw_iw_to_tau": ([P, I, P, LL, LL, P], I),
         "gw_screened_W": ([P, P, I, P], I),
@@ -228,6 +230,18 @@ class Context:
 # --------------------------------------------------------------- the calls ---
 def gw_set_hermitian(ctx, on):
     ctx._check(load().gw_set_hermitian(ctx.h, 1 if on else 0), "gw_set_hermitian")
+
+
+def gw_hermitize(ctx, X, n):
+    """X viewed as [..., n, n] complex128 <- its Hermitian part, in place."""
+    _ptr(X, "X")
+    if X.numel() % (n * n):
+        raise ValueError("gw_hermitize: X must hold whole n x n blocks")
+    nmat = X.numel() // (n * n)
+    for b0 in range(0, nmat, 65535):
+        nb = min(65535, nmat - b0)
+        ctx._check(load().gw_hermitize(ctx.h, ctypes.c_void_p(X.data_ptr() + b0 * n * n * 16),
+                                       int(n), nb), "gw_hermitize")
 
 
 def gw_polarization(ctx, V, G_tau, q0, nq, P0_tau):

@@ -25,6 +25,7 @@ from .adjoint import SigmaDerivatives
 @dataclasses.dataclass
 class NKStats:
     newton_steps: int = 0
+    backtracks: int = 0
     jvps: int = 0
     evaluations: int = 0
     residuals: list = dataclasses.field(default_factory=list)
@@ -141,22 +142,58 @@ class NewtonKrylov:
             if abs(g[j_used]) <= self.gmres_rtol * bnorm:
                 return
 
-    def solve(self, sig_inf, sig_tau, mu0, tol=1e-8, max_steps=20, log=None):
-        """Newton-Krylov from (sig_inf, sig_tau); returns (x, F) flat vectors."""
+    def solve(self, sig_inf, sig_tau, mu0, tol=1e-8, max_steps=20, log=None, forcing=None,
+              max_backtracks=3):
+        """Newton-Krylov from (sig_inf, sig_tau); returns (x, F) flat vectors.
+
+        forcing: None keeps the GMRES relative tolerance fixed; "ew" uses the
+        Eisenstat-Walker choice 2 forcing term eta_k = 0.9 (|F_k| / |F_{k-1}|)^2
+        (2-norms), safeguarded by 0.9 eta_{k-1}^2 and clipped to [gmres_rtol, 0.5],
+        so that early steps are solved loosely and late ones tightly.
+
+        A step that raises max |F| is halved (up to max_backtracks times, one
+        residual evaluation each) before the next Newton step is taken."""
         c = self.ctx
         self.mu = mu0
         x, F, d = self.vec(), self.vec(), self.vec()
         self.pack(sig_inf, sig_tau, x)
-        for it in range(max_steps + 1):
-            self.residual(x, F)
-            res = gw.gw_mix(c, 0.0, None, F, want_diff=True)      # max |F|
-            self.stats.residuals.append(res)
-            if log:
-                log(f"[nk] step {it}: max|F| {res:.3e} mu {self.mu:.10f} jvps {self.stats.jvps}")
-            if res < tol or it == max_steps:
-                break
-            gw.gw_axpby(c, -1.0, F, 0.0, F)                  # right-hand side -F
-            self.gmres(F, d)
-            gw.gw_axpby(c, 1.0, d, 1.0, x)
-            self.stats.newton_steps += 1
+        rtol0 = self.gmres_rtol
+        eta, fn_prev = 0.5, None
+        res_prev, lam, nback = None, 1.0, 0
+        try:
+            for it in range(max_steps + 1):
+                self.residual(x, F)
+                res = gw.gw_mix(c, 0.0, None, F, want_diff=True)      # max |F|
+                if log:
+                    log(f"[nk] step {it}: max|F| {res:.3e} mu {self.mu:.10f} jvps {self.stats.jvps}"
+                        + (f" (step x {lam:g})" if lam != 1.0 else ""))
+                if res_prev is not None and res > res_prev and nback < max_backtracks:
+                    lam *= 0.5                                    # x = x_old + lam d
+                    gw.gw_axpby(c, -lam, d, 1.0, x)
+                    nback += 1
+                    self.stats.backtracks += 1
+                    continue
+                self.stats.residuals.append(res)
+                res_prev, lam, nback = res, 1.0, 0
+                if res < tol or it == max_steps:
+                    break
+                if forcing == "ew":
+                    fn = float(np.sqrt(gw.gw_dot(c, F, F).real))
+                    if fn_prev is not None:
+                        e = 0.9 * (fn / fn_prev) ** 2
+                        safe = 0.9 * eta * eta
+                        eta = max(e, safe) if safe > 0.1 else e
+                    eta = min(max(eta, rtol0), 0.5)
+                    fn_prev = fn
+                    self.gmres_rtol = eta
+                gw.gw_axpby(c, -1.0, F, 0.0, F)                  # right-hand side -F
+                self.gmres(F, d)
+                # the Newton step of a Hermitian residual is Hermitian; drop the
+                # round-off part that is not, which the Hermitian-mode forward
+                # and the real-differentiable mu constraint would not follow
+                gw.gw_hermitize(c, d, c.nao)
+                gw.gw_axpby(c, 1.0, d, 1.0, x)
+                self.stats.newton_steps += 1
+        finally:
+            self.gmres_rtol = rtol0
         return x, F

@@ -58,3 +58,48 @@ def test_newton_krylov_reaches_the_fixed_point():
     assert np.abs(hist[-1][1] - nk_inf).max() < 1e-8
     assert np.abs(hist[-1][2] - nk_tau).max() < 1e-8
     ctx.close()
+
+
+def test_newton_jacobian_matches_finite_differences():
+    """J_F v (Dyson JVP with the mu shift, then the Sigma JVP) against central
+    differences of the residual F along a Hermitian direction; and
+    gw_hermitize against (X + X^H) / 2."""
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.newton import NewtonKrylov
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(mesh=(2, 2, 1), nao=4, naux=12, ntau=12, beta=10.0, seed=31, n_target=4.0)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS)
+    try:
+        path = GWPath(ctx, dev(V), dev(H0), dev(S), wl.n_target)
+        st = path.start(0.0)
+        for _ in range(3):
+            path.step(st)
+        nk = NewtonKrylov(path)
+        x, F0, Jv = nk.vec(), nk.vec(), nk.vec()
+        nk.pack(st.sig_inf, st.sig_tau, x)
+        nk.mu = st.mu
+        rng = np.random.default_rng(8)
+        vi = inp.random_hermitian_tau(rng, 1, wl.nk, wl.nao, 1e-2)[0]
+        vt = inp.random_hermitian_tau(rng, wl.ntau, wl.nk, wl.nao, 1e-2)
+        v = nk.vec()
+        nk.pack(dev(vi), dev(vt), v)
+        nk.residual(x, F0)
+        mu0 = nk.mu
+        nk.jac_vec(v, Jv)
+        h = 1e-5
+        Fp, Fm = nk.vec(), nk.vec()
+        nk.mu = mu0
+        nk.residual(x + h * v, Fp)
+        nk.mu = mu0
+        nk.residual(x - h * v, Fm)
+        rel = ((Fp - Fm) / (2 * h) - Jv).abs().max().item() / Jv.abs().max().item()
+        print("Newton Jacobian vs central differences, rel err", rel)
+        assert rel < 1e-6          # mu is found to a 1e-13 bracket: ~1e-8 noise over 2h
+        # Hermitian part
+        X = dev(inp.circular_gaussian(rng, (5, 3, wl.nao, wl.nao), 1.0))
+        ref = 0.5 * (X + X.conj().transpose(-1, -2))
+        gw.gw_hermitize(ctx, X, wl.nao)
+        assert torch.equal(X, ref)
+    finally:
+        ctx.close()
