@@ -46,6 +46,7 @@ class SigmaDerivatives:
     def _pt(self, G, q):
         """P~^q(tau) -> self.pt_tau and P~^q(i Omega) -> self.pt_w for one q."""
         c, V = self.ctx, self.path.V
+        gw.gw_set_hermitian(c, getattr(self.path, "hermitian", False))
         gw.gw_polarization(c, V, G, q, 1, self.pt_tau)
         gw.gw_tau_to_iw(c, gw.GW_BOSON, self.pt_tau, self.p0_w, batch=1)
         gw.gw_screened_W(c, self.p0_w, self.pt_w)
@@ -117,10 +118,20 @@ class SigmaDerivatives:
 
 class SigmaFunction(torch.autograd.Function):
     """(Sigma_inf, Sigma~) = SigmaFunction.apply(G, derivs); backward is the
-    hand-written VJP above."""
+    hand-written VJP above.
+
+    When derivs.path runs the polarization in Hermitian mode (GWPath's
+    default), G must be Hermitian per (tau, k); the forward checks this and
+    raises ValueError otherwise (build the path with hermitian=False to
+    differentiate at a general complex G).  The VJP itself holds for any G."""
 
     @staticmethod
     def forward(ctx, G, derivs):
+        if getattr(derivs.path, "hermitian", False):
+            dev = (G - G.conj().transpose(-1, -2)).abs().max().item()
+            if dev > 1e-10 * max(1.0, G.abs().max().item()):
+                raise ValueError(f"G is not Hermitian per (tau, k) (deviation {dev:.2e}); the path "
+                                 "computes the polarization in Hermitian mode")
         s_inf, s_tau, Pt_tau, Pt_iw = derivs.forward(G.detach().contiguous())
         ctx.derivs = derivs
         ctx.save_for_backward(G.detach(), Pt_tau, Pt_iw)

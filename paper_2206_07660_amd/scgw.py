@@ -35,7 +35,8 @@ class GWPath:
 
     def __init__(self, ctx: gw.Context, V, H0, S, n_target, alpha=0.5, hermitian=True):
         self.ctx, self.V, self.H0, self.S = ctx, V, H0, S
-        gw.gw_set_hermitian(ctx, hermitian)
+        self.hermitian = bool(hermitian)
+        gw.gw_set_hermitian(ctx, self.hermitian)
         self.n_target, self.alpha = float(n_target), float(alpha)
         c = ctx
         z = dict(dtype=torch.complex128, device="cuda")
@@ -55,6 +56,7 @@ class GWPath:
         out_inf = self.new_inf if out_inf is None else out_inf
         out_tau = self.new_tau if out_tau is None else out_tau
         gw.gw_hf(c, self.V, G_tau, self.gamma, out_inf)
+        gw.gw_set_hermitian(c, self.hermitian)         # the context may be shared
         gw.gw_polarization(c, self.V, G_tau, 0, c.nk, self.P0)
         gw.gw_tau_to_iw(c, gw.GW_BOSON, self.P0, self.P0w, batch=c.nk)
         gw.gw_screened_W(c, self.P0w, self.Pw)

@@ -111,3 +111,29 @@ def test_per_q_recompute_matches_stored(case):
     Gb_q = der_q.vjp(G, None, None, dev(d["Sb_inf"]), dev(d["Sb_tau"]))
     print("per-q vjp rel diff", _rel(Gb_q.cpu().numpy(), Gb.cpu().numpy()))
     assert _rel(Gb_q.cpu().numpy(), Gb.cpu().numpy()) < 1e-12
+
+
+def test_autograd_at_general_complex_G(case):
+    """At a non-Hermitian G the path must run the polarization in its general
+    mode: forward and VJP then match the oracle's autograd twin; a path in
+    Hermitian mode refuses such a G."""
+    from paper_2206_07660_amd.adjoint import SigmaDerivatives, SigmaFunction
+    from paper_2206_07660_amd.scgw import GWPath
+    d = case
+    path_h = d["der"].path
+    rng = np.random.default_rng(23)
+    Gc = d["G"] + 0.05 * inp.circular_gaussian(rng, d["G"].shape, 1.0)
+    with pytest.raises(ValueError):
+        SigmaFunction.apply(dev(Gc).requires_grad_(True), d["der"])
+    path_g = GWPath(path_h.ctx, path_h.V, path_h.H0, path_h.S, path_h.n_target, hermitian=False)
+    der_g = SigmaDerivatives(path_g)
+    G = dev(Gc).requires_grad_(True)
+    s_inf, s_tau = SigmaFunction.apply(G, der_g)
+    Vt, TB, TBp, w = ogt.tensors(d["V"], d["g"])
+    r_inf, r_tau = ogt.sigma_evaluation(Vt, torch.from_numpy(Gc), TB, TBp, w, d["wl"].mesh, NS)
+    assert _rel(s_tau.detach().cpu().numpy(), r_tau.numpy()) < 1e-12
+    assert _rel(s_inf.detach().cpu().numpy(), r_inf.numpy()) < 1e-12
+    loss = (torch.conj(dev(d["Sb_inf"])) * s_inf).sum().real + (torch.conj(dev(d["Sb_tau"])) * s_tau).sum().real
+    loss.backward()
+    ref = ogt.vjp(d["V"], Gc, d["Sb_inf"], d["Sb_tau"], d["g"], d["wl"].mesh, NS)
+    assert _rel(G.grad.cpu().numpy(), ref) < 1e-11
