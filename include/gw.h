@@ -227,7 +227,11 @@ gw_status gw_find_mu(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig
 gw_status gw_mix(gw_ctx* ctx, long long n, double alpha, const gw_z* X_new, gw_z* Y,
                  double* maxdiff);
 
-/* ---- Derivatives of G -> (Sigma_inf, Sigma~) (GW_PREC_FP64 contexts) ----
+/* ---- Derivatives of G -> (Sigma_inf, Sigma~) ----
+ * The JVP calls (gw_polarization2, gw_screened_W_lin, gw_transform_adjoint,
+ * gw_dyson_jvp, with gw_hf and gw_self_energy, which are linear in G and in
+ * P~) run in either precision; the VJP calls that read V (gw_self_energy_vjp,
+ * gw_polarization_vjp, gw_hf_vjp) need a GW_PREC_FP64 context.
  * The map is holomorphic in G, so a vector-Jacobian product (VJP) applies the
  * conjugate-transposed Jacobian to the cotangent; for a real loss L of the
  * outputs this is the gradient dL/dRe + i dL/dIm (torch autograd convention).

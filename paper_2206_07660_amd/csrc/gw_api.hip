@@ -436,9 +436,9 @@ size_t gw_workspace_bytes(const gw_ctx* c, int op, int tau_chunk) {
     case GW_OP_POLARIZATION:
     case GW_OP_SELF_ENERGY:
       if (tau_chunk < 1 || tau_chunk > c->d.ntau) return 0;
-      if (c->d.precision == GW_PREC_FP32)   // complex64 intermediates + complex64 copy of G
+      if (c->d.precision == GW_PREC_FP32)   // complex64 intermediates + complex64 copies of G
         return 2 * align256((size_t)tau_chunk * c->nk * c->sv * 8) +
-               align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
+               2 * align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
       return 2 * align256((size_t)tau_chunk * c->nk * c->sv * z);
     case GW_OP_SCREENED_W:
       if (tau_chunk < 1) return 0;
@@ -532,8 +532,10 @@ gw_status gw_synchronize(gw_ctx* c) {
 static const int kMixedChunk = 512;
 
 // complex64 copy of G(tau) in the workspace (mixed precision only)
-static gw_status g_to_c64(gw_ctx* c, const gw_z* G, void** Gc) {
-  const size_t off = 2 * align256((size_t)c->tc * c->nk * c->sv * 8);
+// complex64 copy of G in slot 0 or 1 of the mixed-precision workspace
+static gw_status g_to_c64(gw_ctx* c, const gw_z* G, void** Gc, int slot = 0) {
+  const size_t off = 2 * align256((size_t)c->tc * c->nk * c->sv * 8) +
+                     (size_t)slot * align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
   *Gc = (char*)c->ws + off;
   HIPCHK(c, to_c64_launch((const double2*)G, (float2*)*Gc, (long long)c->d.ntau * c->nk * c->n2, c->st));
   return GW_OK;
@@ -554,8 +556,6 @@ gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int n
 
 gw_status gw_polarization2(gw_ctx* c, const void* V, const gw_z* Ga, const gw_z* Gb, int q0, int nq,
                            int accumulate, gw_z* P0) {
-  if (c && c->d.precision != GW_PREC_FP64)
-    return fail(c, GW_ERR_ARG, "gw_polarization2 needs a GW_PREC_FP64 context");
   return pol_impl(c, V, Ga, Gb, q0, nq, P0, accumulate != 0);
 }
 
@@ -585,6 +585,10 @@ static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* G
     gw_status s = g_to_c64(c, G, &Gc);
     if (s != GW_OK) return s;
     Gd = Gbd = (const char*)Gc;
+    if (Gb != G) {
+      if ((s = g_to_c64(c, Gb, &Gc, 1)) != GW_OK) return s;
+      Gbd = (const char*)Gc;
+    }
   }
   const int t = f32 ? 1 : 0;
   // P0^q(tau) is Hermitian when G^k(tau) is and V^{k+q,k}(Q) = V^{k,k+q}(Q)^H:
@@ -994,6 +998,13 @@ gw_status gw_find_mu(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf,
 // All of these need a GW_PREC_FP64 context.
 // =========================================================================
 
+// calls that never read V run in either precision
+static gw_status need_grids(gw_ctx* c) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  return GW_OK;
+}
+
 static gw_status need_fp64(gw_ctx* c) {
   if (!c) return GW_ERR_ARG;
   if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
@@ -1002,7 +1013,7 @@ static gw_status need_fp64(gw_ctx* c) {
 }
 
 gw_status gw_screened_W_lin(gw_ctx* c, const gw_z* Pt, const gw_z* X, int nq, int adjoint, gw_z* Y) {
-  gw_status s = need_fp64(c);
+  gw_status s = need_grids(c);
   if (s != GW_OK) return s;
   if (nq < 0 || nq > c->nk) return fail(c, GW_ERR_ARG, "nq out of range");
   if (nq == 0) return GW_OK;
@@ -1040,7 +1051,7 @@ gw_status gw_screened_W_lin(gw_ctx* c, const gw_z* Pt, const gw_z* X, int nq, in
 
 gw_status gw_transform_adjoint(gw_ctx* c, int stat, int inverse, const gw_z* Xin, long long batch,
                                long long R, gw_z* Xout) {
-  gw_status s = need_fp64(c);
+  gw_status s = need_grids(c);
   if (s != GW_OK) return s;
   if (stat != GW_FERMION && stat != GW_BOSON) return fail(c, GW_ERR_ARG, "stat must be 0 or 1");
   if (batch < 0 || R < 0 || batch > 65535 || R > 0x7fffffffLL)
@@ -1328,7 +1339,7 @@ gw_status gw_hermitize(gw_ctx* c, gw_z* X, int n, long long nmat) {
 // ---------------------------------------------------------------- Dyson JVP
 gw_status gw_dyson_jvp(gw_ctx* c, const gw_z* S, const gw_z* G_iw, const gw_z* dSinf,
                        const gw_z* dSig_iw, int fixed_mu, gw_z* dG_iw, double* dmu) {
-  gw_status s = need_fp64(c);
+  gw_status s = need_grids(c);
   if (s != GW_OK) return s;
   if (!S || !G_iw || !dG_iw) return fail(c, GW_ERR_ARG, "NULL array");
   if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_DYSON_JVP, 1))

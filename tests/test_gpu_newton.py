@@ -103,3 +103,44 @@ def test_newton_jacobian_matches_finite_differences():
         assert torch.equal(X, ref)
     finally:
         ctx.close()
+
+
+def test_mixed_precision_newton_krylov():
+    """The JVP runs in a mixed-precision context too (complex64 V, fp32 MFMA
+    polarization and self-energy; transforms, screened-interaction
+    derivative and Dyson JVP in fp64): the mixed JVP matches the fp64 one to
+    1e-5 relative, and a mixed Newton-Krylov solve lands within 1e-6 Ha of
+    the fp64 solution."""
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.adjoint import SigmaDerivatives
+    from paper_2206_07660_amd.newton import NewtonKrylov
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(mesh=(2, 2, 1), nao=4, naux=12, ntau=12, beta=10.0, seed=31, n_target=4.0)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    out = {}
+    for precision in ("fp64", "fp32"):
+        ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, precision=precision)
+        try:
+            Vd = dev(V) if precision == "fp64" else dev(V.astype(np.complex64))
+            path = GWPath(ctx, Vd, dev(H0), dev(S), wl.n_target)
+            st = path.start(0.0)
+            path.step(st)
+            path.step(st)
+            G = st.G_tau.clone()
+            der = SigmaDerivatives(path)
+            si, stau, Pt, Pw = der.forward(G)
+            dG = dev(inp.random_hermitian_tau(np.random.default_rng(9), wl.ntau, wl.nk, wl.nao, 1e-2))
+            di, ds = der.jvp(G, Pt, Pw, dG)
+            nk = NewtonKrylov(path, restart=20, gmres_rtol=1e-8)
+            x, F = nk.solve(st.sig_inf, st.sig_tau, st.mu, tol=1e-8 if precision == "fp32" else 1e-11,
+                            max_steps=12)
+            out[precision] = (di.cpu().numpy(), ds.cpu().numpy(), nk.inf(x).cpu().numpy(),
+                              nk.tau(x).cpu().numpy(), nk.stats.residuals[-1])
+        finally:
+            ctx.close()
+    a, b = out["fp64"], out["fp32"]
+    rel = lambda u, v: np.abs(u - v).max() / np.abs(v).max()
+    print("mixed JVP rel diff", rel(b[0], a[0]), rel(b[1], a[1]), "final residuals", a[4], b[4])
+    assert rel(b[0], a[0]) < 1e-5 and rel(b[1], a[1]) < 1e-5
+    assert b[4] < 1e-8
+    assert np.abs(b[2] - a[2]).max() < 1e-6 and np.abs(b[3] - a[3]).max() < 1e-6
