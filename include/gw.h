@@ -153,16 +153,20 @@ gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
 gw_status gw_polarization(gw_ctx* ctx, const void* V, const gw_z* G_tau, int q0, int nq,
                           gw_z* P0_tau);   /* V: gw_z (GW_PREC_FP64) or gw_c (GW_PREC_FP32) */
 
-/* Hermitian mode of gw_polarization (off after gw_create).  With on != 0 the
- * caller states that every G_tau passed to gw_polarization is Hermitian in
- * its orbital indices at each tau and k (true of the Green's function of a
- * Hermitian H0, S and Sigma) and that V obeys V^{k+q,k}(Q) = V^{k,k+q}(Q)^H
- * (Eq. tilde_P0_tau's pair relation).  P0^q(tau) is then Hermitian: the
- * trace of the bubble for (Q', Q) is the complex conjugate of the one for
- * (Q, Q').  Only the output tiles on and above the diagonal are contracted
- * and the rest is filled by conjugation.  Results for inputs that break
- * either property are undefined in this mode.  gw_polarization2 ignores it. */
-gw_status gw_set_hermitian(gw_ctx* ctx, int on);
+/* Hermitian mode of the polarization (off after gw_create).  mode is a bit
+ * set: GW_HERM_FORWARD states that every G_tau passed to gw_polarization is
+ * Hermitian in its orbital indices at each tau and k (true of the Green's
+ * function of a Hermitian H0, S and Sigma); GW_HERM_TWO_SLOT states the same
+ * of both G_a and G_b of every gw_polarization2 call (true of G and of the
+ * Dyson response dG to a Hermitian dSigma).  With V^{k+q,k}(Q) =
+ * V^{k,k+q}(Q)^H (Eq. tilde_P0_tau's pair relation), the conjugate of the
+ * bubble trace for (Q, Q') is then the trace for (Q', Q), so P0^q(tau) (and
+ * each two-slot term) is Hermitian: only the output tiles on and above the
+ * diagonal are contracted and the rest is filled by conjugation (also when
+ * accumulating, where the previous contents must be Hermitian as well).
+ * Results for inputs that break these properties are undefined.          */
+enum { GW_HERM_FORWARD = 1, GW_HERM_TWO_SLOT = 2 };
+gw_status gw_set_hermitian(gw_ctx* ctx, int mode);
 
 /* Eqs. tau_to_iw / P0t_to_P0w: X_iw[b][n][r] = sum_i T[n][i] X_tau[b][i][r]
  * for b < batch, r < R, with T the fermionic (stat = GW_FERMION, nw = nw_f)

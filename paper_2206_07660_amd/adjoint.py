@@ -72,8 +72,12 @@ class SigmaDerivatives:
             gw.gw_self_energy(c, V, G, self.pt_tau, q, 1, s_tau)
         return s_inf, s_tau, None, None
 
-    def jvp(self, G, Pt_tau, Pt_iw, dG):
+    def jvp(self, G, Pt_tau, Pt_iw, dG, hermitian_dG=False):
+        """hermitian_dG: dG is Hermitian per (tau, k), like G (e.g. the Dyson
+        response to a Hermitian dSigma); with a Hermitian-mode path the two
+        polarization terms are then contracted as Hermitian products."""
         c, V = self.ctx, self.path.V
+        herm = getattr(self.path, "hermitian", False)
         z = dict(dtype=torch.complex128, device="cuda")
         d_inf = torch.empty(c.k_shape(), **z)
         gw.gw_hf(c, V, dG, None, d_inf)
@@ -81,6 +85,7 @@ class SigmaDerivatives:
         gw.gw_mix(c, 1.0, None, d_tau)
         dP = self.buf_tau
         for q0, nq, pt_tau, pt_w in self._slices(G, Pt_tau, Pt_iw):
+            gw.gw_set_hermitian(c, herm, two_slot=herm and hermitian_dG)
             gw.gw_polarization2(c, V, dG, G, q0, nq, dP)
             gw.gw_polarization2(c, V, G, dG, q0, nq, dP, accumulate=True)
             gw.gw_tau_to_iw(c, gw.GW_BOSON, dP, self.buf_w1, batch=nq)

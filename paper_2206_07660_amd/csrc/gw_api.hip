@@ -29,7 +29,7 @@ struct gw_ctx {
   std::vector<int> plus;   // host copy of the k+q table
   bool check_bounds = false;
   int tile_cfg = -1;       // tile configuration of the large contractions (-1: default)
-  bool herm = false;       // gw_set_hermitian: G Hermitian, V pair-Hermitian
+  int herm = 0;            // gw_set_hermitian: GW_HERM_* bits
   // measurement: event pairs per kernel class while profiling is on
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KC_COUNT];
@@ -542,26 +542,27 @@ static gw_status g_to_c64(gw_ctx* c, const gw_z* G, void** Gc, int slot = 0) {
 }
 
 static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Gb, int q0, int nq,
-                          gw_z* P0, bool accumulate);
+                          gw_z* P0, bool accumulate, bool two_slot);
 
-gw_status gw_set_hermitian(gw_ctx* c, int on) {
+gw_status gw_set_hermitian(gw_ctx* c, int mode) {
   if (!c) return GW_ERR_ARG;
-  c->herm = on != 0;
+  if (mode & ~(GW_HERM_FORWARD | GW_HERM_TWO_SLOT)) return fail(c, GW_ERR_ARG, "unknown Hermitian-mode bits");
+  c->herm = mode;
   return GW_OK;
 }
 
 gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int nq, gw_z* P0) {
-  return pol_impl(c, V, G, G, q0, nq, P0, false);
+  return pol_impl(c, V, G, G, q0, nq, P0, false, false);
 }
 
 gw_status gw_polarization2(gw_ctx* c, const void* V, const gw_z* Ga, const gw_z* Gb, int q0, int nq,
                            int accumulate, gw_z* P0) {
-  return pol_impl(c, V, Ga, Gb, q0, nq, P0, accumulate != 0);
+  return pol_impl(c, V, Ga, Gb, q0, nq, P0, accumulate != 0, true);
 }
 
 // G fills the tau slot (G^{k+q}(tau_i)), Gb the mirrored slot (G^k(tau_{ntau-1-i})).
 static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Gb, int q0, int nq,
-                          gw_z* P0, bool accumulate) {
+                          gw_z* P0, bool accumulate, bool two_slot) {
   if (!c) return GW_ERR_ARG;
   if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
   if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
@@ -591,9 +592,11 @@ static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* G
     }
   }
   const int t = f32 ? 1 : 0;
-  // P0^q(tau) is Hermitian when G^k(tau) is and V^{k+q,k}(Q) = V^{k,k+q}(Q)^H:
-  // then only the tiles on and above the diagonal are contracted.
-  const bool herm = c->herm && G == Gb && !accumulate;
+  // P0^q(tau) is Hermitian when G^k(tau) is and V^{k+q,k}(Q) = V^{k,k+q}(Q)^H,
+  // and so is each two-slot term P0[Ga, Gb] for Hermitian Ga, Gb: then only
+  // the tiles on and above the diagonal are contracted (accumulating into an
+  // upper triangle and refilling the lower one keeps a Hermitian sum).
+  const bool herm = (c->herm & (two_slot ? GW_HERM_TWO_SLOT : GW_HERM_FORWARD)) != 0;
   for (int q = q0; q < q0 + nq; ++q) {
     const char* Aq = Vd + (size_t)q * nk * sv * ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {

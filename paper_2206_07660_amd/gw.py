@@ -228,8 +228,14 @@ class Context:
 
 
 # --------------------------------------------------------------- the calls ---
-def gw_set_hermitian(ctx, on):
-    ctx._check(load().gw_set_hermitian(ctx.h, 1 if on else 0), "gw_set_hermitian")
+GW_HERM_FORWARD, GW_HERM_TWO_SLOT = 1, 2
+
+
+def gw_set_hermitian(ctx, on, two_slot=False):
+    """on: gw_polarization's G is Hermitian; two_slot: so are both G of
+    gw_polarization2 (see gw.h)."""
+    mode = (GW_HERM_FORWARD if on else 0) | (GW_HERM_TWO_SLOT if two_slot else 0)
+    ctx._check(load().gw_set_hermitian(ctx.h, mode), "gw_set_hermitian")
 
 
 def gw_hermitize(ctx, X, n):

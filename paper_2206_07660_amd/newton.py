@@ -83,7 +83,10 @@ class NewtonKrylov:
         gw.gw_tau_to_iw(c, gw.GW_FERMION, self.tau(v), self.sig_iw)
         gw.gw_dyson_jvp(c, p.S, self.G_iw, self.inf(v), self.sig_iw, self.dG_iw)
         gw.gw_iw_to_tau(c, gw.GW_FERMION, self.dG_iw, self.dG_tau)
-        d_inf, d_tau = self.der.jvp(self.G_tau, self.Pt_tau, self.Pt_iw, self.dG_tau)
+        # the Krylov directions are Hermitian up to round-off, and so is dG
+        gw.gw_hermitize(c, self.dG_tau, c.nao)
+        d_inf, d_tau = self.der.jvp(self.G_tau, self.Pt_tau, self.Pt_iw, self.dG_tau,
+                                    hermitian_dG=True)
         self.stats.jvps += 1
         self.pack(d_inf, d_tau, out)
         gw.gw_axpby(c, -1.0, v, 1.0, out)
