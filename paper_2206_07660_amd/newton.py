@@ -14,6 +14,7 @@ the small Hessenberg least-squares problem of GMRES is solved on the host.
 from __future__ import annotations
 
 import dataclasses
+import time
 
 import numpy as np
 import torch
@@ -26,13 +27,22 @@ from .adjoint import SigmaDerivatives
 class NKStats:
     newton_steps: int = 0
     backtracks: int = 0
+    mu_fallback: bool = False
     jvps: int = 0
     evaluations: int = 0
     residuals: list = dataclasses.field(default_factory=list)
 
 
 class NewtonKrylov:
-    def __init__(self, path, restart=20, gmres_rtol=1e-6, max_restarts=10, per_q=False):
+    def __init__(self, path, restart=20, gmres_rtol=1e-6, max_restarts=10, per_q=False, log=None,
+                 fixed_mu_jvp=False):
+        self.log = log            # optional progress callback, one line per JVP
+        # fixed_mu_jvp: leave out the mu shift of the Dyson JVP.  In a gapped
+        # system at low temperature N_e hardly depends on mu inside the gap,
+        # so the shift that keeps N_e fixed is a ratio of two exponentially
+        # small numbers, while G itself hardly depends on mu there either.
+        self.fixed_mu_jvp = fixed_mu_jvp
+        self.last_dmu = 0.0
         self.path = path
         self.ctx = path.ctx
         self.der = SigmaDerivatives(path, per_q=per_q)
@@ -81,13 +91,16 @@ class NewtonKrylov:
         """out = J_F v = dSigma_GW[dG(v)] - v at the last residual point."""
         c, p = self.ctx, self.path
         gw.gw_tau_to_iw(c, gw.GW_FERMION, self.tau(v), self.sig_iw)
-        gw.gw_dyson_jvp(c, p.S, self.G_iw, self.inf(v), self.sig_iw, self.dG_iw)
+        self.last_dmu = gw.gw_dyson_jvp(c, p.S, self.G_iw, self.inf(v), self.sig_iw, self.dG_iw,
+                                        fixed_mu=self.fixed_mu_jvp)
         gw.gw_iw_to_tau(c, gw.GW_FERMION, self.dG_iw, self.dG_tau)
         # the Krylov directions are Hermitian up to round-off, and so is dG
         gw.gw_hermitize(c, self.dG_tau, c.nao)
         d_inf, d_tau = self.der.jvp(self.G_tau, self.Pt_tau, self.Pt_iw, self.dG_tau,
                                     hermitian_dG=True)
         self.stats.jvps += 1
+        if self.log:
+            self.log(f"[nk] JVP {self.stats.jvps} (dmu {self.last_dmu:.3e})")
         self.pack(d_inf, d_tau, out)
         gw.gw_axpby(c, -1.0, v, 1.0, out)
 
@@ -146,7 +159,7 @@ class NewtonKrylov:
                 return
 
     def solve(self, sig_inf, sig_tau, mu0, tol=1e-8, max_steps=20, log=None, forcing=None,
-              max_backtracks=3):
+              max_backtracks=3, deadline=None):
         """Newton-Krylov from (sig_inf, sig_tau); returns (x, F) flat vectors.
 
         forcing: None keeps the GMRES relative tolerance fixed; "ew" uses the
@@ -155,7 +168,12 @@ class NewtonKrylov:
         so that early steps are solved loosely and late ones tightly.
 
         A step that raises max |F| is halved (up to max_backtracks times, one
-        residual evaluation each) before the next Newton step is taken."""
+        residual evaluation each) before the next Newton step is taken.  If
+        no halving helps, the solve returns to the previous point and, the
+        first time, continues with the mu shift left out of the JVP (see
+        fixed_mu_jvp); a second failure ends the solve there.
+        deadline: a time.perf_counter() value after which no further Newton
+        step is started (the last residual is returned)."""
         c = self.ctx
         self.mu = mu0
         x, F, d = self.vec(), self.vec(), self.vec()
@@ -170,15 +188,33 @@ class NewtonKrylov:
                 if log:
                     log(f"[nk] step {it}: max|F| {res:.3e} mu {self.mu:.10f} jvps {self.stats.jvps}"
                         + (f" (step x {lam:g})" if lam != 1.0 else ""))
-                if res_prev is not None and res > res_prev and nback < max_backtracks:
-                    lam *= 0.5                                    # x = x_old + lam d
-                    gw.gw_axpby(c, -lam, d, 1.0, x)
-                    nback += 1
-                    self.stats.backtracks += 1
+                if res_prev is not None and res > res_prev:
+                    if nback < max_backtracks:
+                        lam *= 0.5                                # x = x_old + lam d
+                        gw.gw_axpby(c, -lam, d, 1.0, x)
+                        nback += 1
+                        self.stats.backtracks += 1
+                        continue
+                    gw.gw_axpby(c, -lam, d, 1.0, x)               # back to x_old
+                    if self.fixed_mu_jvp:
+                        if log:
+                            log("[nk] no descent along the Newton step; stopping at the previous point")
+                        self.residual(x, F)
+                        break
+                    if log:
+                        log("[nk] no descent along the Newton step; continuing with the mu shift "
+                            "left out of the JVP")
+                    self.fixed_mu_jvp = True
+                    self.stats.mu_fallback = True
+                    res_prev, lam, nback = None, 1.0, 0
                     continue
                 self.stats.residuals.append(res)
                 res_prev, lam, nback = res, 1.0, 0
                 if res < tol or it == max_steps:
+                    break
+                if deadline is not None and time.perf_counter() > deadline:
+                    if log:
+                        log("[nk] wall-clock budget reached")
                     break
                 if forcing == "ew":
                     fn = float(np.sqrt(gw.gw_dot(c, F, F).real))
