@@ -103,8 +103,6 @@ struct DysonArgs {
 };
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st);
-hipError_t wdyson_launch(const double2* P0, double2* X, double2* work, int n, long long nmat,
-                         int* flag, hipStream_t st);
 hipError_t dyson_launch(const DysonArgs& a, int nw, hipStream_t st);
 hipError_t sum_launch(const double* x, long long n, double scale, double* out, hipStream_t st);
 hipError_t trace_launch(const double2* g, const double2* S, int n, int nk, double* part,

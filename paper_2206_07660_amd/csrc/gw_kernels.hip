@@ -4,9 +4,13 @@
 //                per-operand index maps, used for every contraction of the
 //                polarization and self-energy chains, the tau <-> i omega
 //                transforms and the Hartree-Fock terms.
-//  * wdyson_k    (I - P0) X = P0 by LU with partial pivoting (Eq. tilde_P_omega).
+//                fp32 MFMA variant for the mixed-precision path.
+//  * wlu_*_k     panel and triangular kernels of the blocked LU of I - P0
+//                (Eq. tilde_P_omega); its trailing updates are zgemm_k calls.
 //  * dyson_k     G = [(i w + mu) S - H0 - Sigma]^{-1} by Gauss-Jordan (Eq. Dyson),
 //                with the electron-count partials of gamma = -G(beta^-).
+//  * herm_fill_k, herm_avg_k   Hermitian fill / Hermitian part of matrices.
+//  * small reductions and vector kernels (sums, traces, mixing, axpby, dot).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -759,138 +763,6 @@ hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st) {
   if (nmat > 65535 || (long long)n * n > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   const unsigned bx = (unsigned)(((long long)n * n + 255) / 256);
   herm_fill_k<<<dim3(bx, (unsigned)nmat, 1), 256, 0, st>>>(P, n);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// (I - P0) X = P0, one workgroup per matrix.  The LU factors of I - P0 live
-// in `work`; the right-hand side is X itself.  Row pivoting by the largest
-// |re| + |im| (smallest row index on ties).
-__global__ void __launch_bounds__(1024) wdyson_k(const double2* __restrict__ P0, double2* X,
-                                                 double2* work, int n, int* flag) {
-  const size_t nn = (size_t)n * n;
-  const double2* P = P0 + blockIdx.x * nn;
-  double2* Amat = work + blockIdx.x * nn;
-  double2* Bmat = X + blockIdx.x * nn;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  __shared__ int piv_s;
-  __shared__ double2 pinv_s;
-
-  for (size_t e = tid; e < nn; e += nt) {
-    const int r = (int)(e / n), c = (int)(e % n);
-    const double2 p = P[e];
-    Amat[e] = double2{(r == c ? 1.0 : 0.0) - p.x, -p.y};
-    Bmat[e] = p;
-  }
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double best = -1.0;
-    int bi = j;
-    for (int r = j + tid; r < n; r += nt) {
-      const double2 a = Amat[(size_t)r * n + j];
-      const double v = fabs(a.x) + fabs(a.y);
-      if (v > best) { best = v; bi = r; }
-    }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double o = sv[tid + s];
-        const int oi = si[tid + s];
-        if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) { sv[tid] = o; si[tid] = oi; }
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      piv_s = si[0];
-      if (!(sv[0] > 0.0)) atomicOr(flag, 1);
-    }
-    __syncthreads();
-    const int p = piv_s;
-    if (p != j) {
-      for (int c = tid; c < n; c += nt) {
-        double2 t = Amat[(size_t)j * n + c];
-        Amat[(size_t)j * n + c] = Amat[(size_t)p * n + c];
-        Amat[(size_t)p * n + c] = t;
-        t = Bmat[(size_t)j * n + c];
-        Bmat[(size_t)j * n + c] = Bmat[(size_t)p * n + c];
-        Bmat[(size_t)p * n + c] = t;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const double2 a = Amat[(size_t)j * n + j];
-      const double den = a.x * a.x + a.y * a.y;
-      pinv_s = den > 0.0 ? double2{a.x / den, -a.y / den} : double2{0.0, 0.0};
-    }
-    __syncthreads();
-    const double2 pi = pinv_s;
-    for (int r = j + 1 + tid; r < n; r += nt) {
-      const double2 a = Amat[(size_t)r * n + j];
-      Amat[(size_t)r * n + j] = double2{a.x * pi.x - a.y * pi.y, a.x * pi.y + a.y * pi.x};
-    }
-    __syncthreads();
-    const int rows = n - j - 1;
-    const size_t cntA = (size_t)rows * (n - j - 1);
-    for (size_t e = tid; e < cntA; e += nt) {
-      const int r = j + 1 + (int)(e / (n - j - 1));
-      const int c = j + 1 + (int)(e % (n - j - 1));
-      const double2 l = Amat[(size_t)r * n + j];
-      const double2 u = Amat[(size_t)j * n + c];
-      double2 a = Amat[(size_t)r * n + c];
-      a.x -= l.x * u.x - l.y * u.y;
-      a.y -= l.x * u.y + l.y * u.x;
-      Amat[(size_t)r * n + c] = a;
-    }
-    const size_t cntB = (size_t)rows * n;
-    for (size_t e = tid; e < cntB; e += nt) {
-      const int r = j + 1 + (int)(e / n);
-      const int c = (int)(e % n);
-      const double2 l = Amat[(size_t)r * n + j];
-      const double2 u = Bmat[(size_t)j * n + c];
-      double2 b = Bmat[(size_t)r * n + c];
-      b.x -= l.x * u.x - l.y * u.y;
-      b.y -= l.x * u.y + l.y * u.x;
-      Bmat[(size_t)r * n + c] = b;
-    }
-    __syncthreads();
-  }
-  // back substitution with the upper factor
-  for (int j = n - 1; j >= 0; --j) {
-    if (tid == 0) {
-      const double2 a = Amat[(size_t)j * n + j];
-      const double den = a.x * a.x + a.y * a.y;
-      pinv_s = den > 0.0 ? double2{a.x / den, -a.y / den} : double2{0.0, 0.0};
-    }
-    __syncthreads();
-    const double2 pi = pinv_s;
-    for (int c = tid; c < n; c += nt) {
-      const double2 b = Bmat[(size_t)j * n + c];
-      Bmat[(size_t)j * n + c] = double2{b.x * pi.x - b.y * pi.y, b.x * pi.y + b.y * pi.x};
-    }
-    __syncthreads();
-    const size_t cnt = (size_t)j * n;
-    for (size_t e = tid; e < cnt; e += nt) {
-      const int r = (int)(e / n), c = (int)(e % n);
-      const double2 u = Amat[(size_t)r * n + j];
-      const double2 x = Bmat[(size_t)j * n + c];
-      double2 b = Bmat[(size_t)r * n + c];
-      b.x -= u.x * x.x - u.y * x.y;
-      b.y -= u.x * x.y + u.y * x.x;
-      Bmat[(size_t)r * n + c] = b;
-    }
-    __syncthreads();
-  }
-}
-
-hipError_t wdyson_launch(const double2* P0, double2* X, double2* work, int n, long long nmat,
-                         int* flag, hipStream_t st) {
-  if (nmat <= 0) return hipSuccess;
-  if (nmat > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  wdyson_k<<<(unsigned)nmat, 1024, 0, st>>>(P0, X, work, n, flag);
   return hipGetLastError();
 }
 
