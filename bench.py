@@ -141,10 +141,12 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
 
 
 def compare_solvers(path, wl, tol):
-    """Damped fixed point vs Newton-Krylov (GMRES(20)) from the same start to
-    max |Sigma[G(x)] - x| < tol; both on the fp64 path."""
+    """Damped fixed point, Pulay DIIS and Newton-Krylov (GMRES(20)) to
+    max |Sigma[G(x)] - x| < tol, all on the fp64 path; the fixed point and
+    DIIS start from G0, Newton-Krylov after two damped steps from G0."""
     import torch
     from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.diis import DIIS
     from paper_2206_07660_amd.newton import NewtonKrylov
     flops = contraction_flops(wl.nk, wl.nao, wl.naux, wl.ntau)
     torch.cuda.synchronize()
@@ -180,7 +182,16 @@ def compare_solvers(path, wl, tol):
     torch.cuda.synchronize()
     t_nkq = time.perf_counter() - t0
     dq = max((nkq.inf(xq) - nk.inf(x)).abs().max().item(), (nkq.tau(xq) - nk.tau(x)).abs().max().item())
-    return {"metric": "scGW solve to equal residual: damped fixed point vs Newton-Krylov (fp64)",
+    # Pulay DIIS on the same residual, from the same start as the fixed point
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st4 = path.start(0.0)
+    dz = DIIS(path, depth=6)
+    xd, Fd = dz.solve(st4.sig_inf, st4.sig_tau, st4.mu, tol=tol, max_iter=100, log=log)
+    torch.cuda.synchronize()
+    t_diis = time.perf_counter() - t0
+    dd = max((dz.inf(xd) - fp_inf).abs().max().item(), (dz.tau(xd) - fp_tau).abs().max().item())
+    return {"metric": "scGW solve to equal residual: damped fixed point vs DIIS vs Newton-Krylov (fp64)",
             "workload": wl.name, "tol_max_abs_residual_Ha": tol,
             "fixed_point": {"iterations": n_fp, "sigma_evaluations": n_fp, "seconds": t_fp,
                             "final_dsigma": st.dsig},
@@ -192,7 +203,12 @@ def compare_solvers(path, wl, tol):
                                               "sigma_evaluations": nkq.stats.evaluations + 2,
                                               "jvps": nkq.stats.jvps, "seconds": t_nkq,
                                               "max_abs_sigma_difference_vs_stored_Ha": dq},
+            "diis": {"depth": dz.core.depth, "iterations": dz.stats.iterations,
+                     "sigma_evaluations": dz.stats.evaluations, "seconds": t_diis,
+                     "residuals": dz.stats.residuals, "max_abs_sigma_difference_vs_fixed_point_Ha": dd},
             "speedup_nk_over_fixed_point": t_fp / t_nk,
+            "speedup_diis_over_fixed_point": t_fp / t_diis,
+            "speedup_nk_over_diis": t_diis / t_nk,
             "max_abs_sigma_difference_Ha": d,
             "gflop_per_sigma_evaluation": flops / 1e9}
 
@@ -208,7 +224,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (fp32 MFMA) comparison")
     ap.add_argument("--compare-solvers", action="store_true",
-                    help="instead of the step benchmark: damped fixed point vs Newton-Krylov "
+                    help="instead of the step benchmark: damped fixed point vs DIIS vs Newton-Krylov "
                          "to the same residual (default workload ad-3x3x3)")
     ap.add_argument("--tol", type=float, default=1e-8)
     args = ap.parse_args()

@@ -218,10 +218,29 @@ gw_status gw_dyson_G(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig
  * On return *mu_inout is the midpoint, G_iw (may be NULL) holds G at that mu,
  * G_tau (may be NULL) its transform to the tau nodes, *n_out (may be NULL)
  * the electron count there.  n_target outside (0, ns*nao) is GW_ERR_ARG; a
- * bracket that cannot be found is GW_ERR_NOCONV.  Synchronises.             */
+ * bracket that cannot be found is GW_ERR_NOCONV.  With a window set by
+ * gw_set_mu_window the result is instead *mu_inout itself if its count is
+ * within the window of n_target, else the midpoint of the two roots of
+ * N_e(mu) = n_target -/+ window (each found the same way).  Synchronises.   */
 gw_status gw_find_mu(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig_inf,
                      const gw_z* Sig_iw, double n_target, double tol, double* mu_inout,
                      gw_z* G_iw, gw_z* G_tau, double* n_out);
+
+/* Electron-count window of the mu search (Sec. IV.A adjusts mu until the
+ * count is within a threshold, 1e-9 there).  ne_tol > 0: gw_find_mu keeps
+ * the mu it is given when |N_e(mu) - n_target| <= ne_tol there, and
+ * otherwise returns the midpoint of the interval of mu where that holds
+ * (ne_tol clamped to half the distance of n_target from 0 and from ns*nao);
+ * for a metal that interval is narrow and its midpoint is the root, for a
+ * gapped system it lies mid-gap.  ne_tol = 0 (the default): the root.
+ * Why: in a gapped system at low temperature the count is flat across the
+ * gap up to the representation error of the sparse grids, so the root lies
+ * where a Fermi tail cancels that error, near a band edge, and moves far
+ * with small changes of Sigma; and every mu in the gap gives nearly a
+ * solution (G(tau) moves with mu roughly as exp(dmu tau)), a direction in
+ * which a self-consistency iteration hardly contracts unless mu is held.
+ * A negative or non-finite ne_tol is GW_ERR_ARG.                            */
+gw_status gw_set_mu_window(gw_ctx* ctx, double ne_tol);
 
 /* Damped update and convergence measure of the scGW loop (Sec. IV.A):
  * Y <- (1 - alpha) Y + alpha X_new over n complex elements.  X_new may be

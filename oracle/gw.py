@@ -185,29 +185,44 @@ def count_from_iw(G_iw, S, grids, ns):
     return electron_count(density_matrix(to_tau(grids.TFp, G_iw), grids.w), S, ns)
 
 
-def find_mu(H0, S, Sig_inf, Sig_iw, n_target, grids, ns, mu0=0.0, tol=1e-13, maxit=400):
-    """Chemical potential with N_e(mu) = n_target (Sec. IV.A; reading R9)."""
+def find_mu(H0, S, Sig_inf, Sig_iw, n_target, grids, ns, mu0=0.0, tol=1e-13, maxit=400,
+            window=0.0):
+    """Chemical potential with N_e(mu) = n_target (Sec. IV.A; reading R9).
+    window > 0 (Sec. IV.A adjusts mu until the count meets a threshold): mu0
+    itself when its count is within w of the target, else the midpoint of
+    the interval of mu where it is, i.e. of the roots of N_e = n_target - w
+    and n_target + w; w = min(window, n_target / 2, (ns nao - n_target) / 2)."""
     def ne(mu):
         return count_from_iw(dyson(H0, S, Sig_inf, Sig_iw, mu, grids.wF), S, grids, ns)
 
-    lo, hi = mu0 - 1.0, mu0 + 1.0
-    step = 1.0
-    while ne(lo) > n_target:
-        step *= 2.0
-        lo -= step
-    step = 1.0
-    while ne(hi) < n_target:
-        step *= 2.0
-        hi += step
-    it = 0
-    while hi - lo > tol and it < maxit:
-        mid = 0.5 * (lo + hi)
-        if ne(mid) < n_target:
-            lo = mid
+    def root(target):
+        lo, hi = mu0 - 1.0, mu0 + 1.0
+        step = 1.0
+        while ne(lo) > target:
+            step *= 2.0
+            lo -= step
+        step = 1.0
+        while ne(hi) < target:
+            step *= 2.0
+            hi += step
+        it = 0
+        while hi - lo > tol and it < maxit:
+            mid = 0.5 * (lo + hi)
+            if ne(mid) < target:
+                lo = mid
+            else:
+                hi = mid
+            it += 1
+        return 0.5 * (lo + hi)
+
+    if window > 0.0:
+        w = min(window, 0.5 * n_target, 0.5 * (ns * H0.shape[-1] - n_target))
+        if abs(ne(mu0) - n_target) <= w:
+            mu = mu0
         else:
-            hi = mid
-        it += 1
-    mu = 0.5 * (lo + hi)
+            mu = 0.5 * (root(n_target - w) + root(n_target + w))
+    else:
+        mu = root(n_target)
     G_iw = dyson(H0, S, Sig_inf, Sig_iw, mu, grids.wF)
     return mu, G_iw, count_from_iw(G_iw, S, grids, ns)
 

@@ -30,6 +30,7 @@ struct gw_ctx {
   bool check_bounds = false;
   int tile_cfg = -1;       // tile configuration of the large contractions (-1: default)
   int herm = 0;            // gw_set_hermitian: GW_HERM_* bits
+  double mu_window = 0.0;  // gw_set_mu_window: electron-count window (0: exact root)
   // measurement: event pairs per kernel class while profiling is on
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KC_COUNT];
@@ -551,6 +552,13 @@ gw_status gw_set_hermitian(gw_ctx* c, int mode) {
   return GW_OK;
 }
 
+gw_status gw_set_mu_window(gw_ctx* c, double ne_tol) {
+  if (!c) return GW_ERR_ARG;
+  if (!std::isfinite(ne_tol) || ne_tol < 0.0) return fail(c, GW_ERR_ARG, "ne_tol must be finite and >= 0");
+  c->mu_window = ne_tol;
+  return GW_OK;
+}
+
 gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int nq, gw_z* P0) {
   return pol_impl(c, V, G, G, q0, nq, P0, false, false);
 }
@@ -955,33 +963,55 @@ gw_status gw_find_mu(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf,
   if (!(tol > 0.0)) tol = 1e-13;
   HIPCHK(c, zero_flag_launch(c->dflag, c->st));
   const double mu0 = *mu_inout;
-  double lo = mu0 - 1.0, hi = mu0 + 1.0, n = 0.0, step = 1.0;
+  double n = 0.0;
   gw_status s;
-  int it = 0;
-  for (;;) {
-    if ((s = count_at(c, H0, S, Sinf, Siw, lo, nullptr, &n)) != GW_OK) return s;
-    if (!(n > n_target)) break;
-    step *= 2.0;
-    lo -= step;
-    if (++it > 60) return fail(c, GW_ERR_NOCONV, "mu search: no lower bracket");
+  // root of N_e(mu) = target by bracket expansion from mu0 +/- 1 Ha and bisection
+  auto root = [&](double target, double* out) -> gw_status {
+    double lo = mu0 - 1.0, hi = mu0 + 1.0, step = 1.0, m = 0.0;
+    gw_status r;
+    int it = 0;
+    for (;;) {
+      if ((r = count_at(c, H0, S, Sinf, Siw, lo, nullptr, &m)) != GW_OK) return r;
+      if (!(m > target)) break;
+      step *= 2.0;
+      lo -= step;
+      if (++it > 60) return fail(c, GW_ERR_NOCONV, "mu search: no lower bracket");
+    }
+    step = 1.0;
+    it = 0;
+    for (;;) {
+      if ((r = count_at(c, H0, S, Sinf, Siw, hi, nullptr, &m)) != GW_OK) return r;
+      if (!(m < target)) break;
+      step *= 2.0;
+      hi += step;
+      if (++it > 60) return fail(c, GW_ERR_NOCONV, "mu search: no upper bracket");
+    }
+    it = 0;
+    while (hi - lo > tol && it < 400) {
+      const double mid = 0.5 * (lo + hi);
+      if ((r = count_at(c, H0, S, Sinf, Siw, mid, nullptr, &m)) != GW_OK) return r;
+      if (m < target) lo = mid; else hi = mid;
+      ++it;
+    }
+    *out = 0.5 * (lo + hi);
+    return GW_OK;
+  };
+  double mu = 0.0;
+  if (c->mu_window > 0.0) {
+    const double w = std::min(c->mu_window, 0.5 * std::min(n_target, (double)c->d.ns * c->d.nao - n_target));
+    // keep mu0 when its count is inside the window, else the window's midpoint
+    if ((s = count_at(c, H0, S, Sinf, Siw, mu0, nullptr, &n)) != GW_OK) return s;
+    if (std::fabs(n - n_target) <= w) {
+      mu = mu0;
+    } else {
+      double m_lo = 0.0, m_hi = 0.0;
+      if ((s = root(n_target - w, &m_lo)) != GW_OK) return s;
+      if ((s = root(n_target + w, &m_hi)) != GW_OK) return s;
+      mu = 0.5 * (m_lo + m_hi);
+    }
+  } else {
+    if ((s = root(n_target, &mu)) != GW_OK) return s;
   }
-  step = 1.0;
-  it = 0;
-  for (;;) {
-    if ((s = count_at(c, H0, S, Sinf, Siw, hi, nullptr, &n)) != GW_OK) return s;
-    if (!(n < n_target)) break;
-    step *= 2.0;
-    hi += step;
-    if (++it > 60) return fail(c, GW_ERR_NOCONV, "mu search: no upper bracket");
-  }
-  it = 0;
-  while (hi - lo > tol && it < 400) {
-    const double mid = 0.5 * (lo + hi);
-    if ((s = count_at(c, H0, S, Sinf, Siw, mid, nullptr, &n)) != GW_OK) return s;
-    if (n < n_target) lo = mid; else hi = mid;
-    ++it;
-  }
-  const double mu = 0.5 * (lo + hi);
   if ((s = count_at(c, H0, S, Sinf, Siw, mu, G_iw, &n)) != GW_OK) return s;
   if ((s = read_flag(c, "find_mu")) != GW_OK) return s;
   *mu_inout = mu;

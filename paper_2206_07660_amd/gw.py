@@ -29,7 +29,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
            "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
-           "gw_hermitize"]
+           "gw_hermitize", "gw_set_mu_window"]
 
 
 class GwError(RuntimeError):
@@ -65,6 +65,7 @@ def load():
         "gw_set_workspace": ([P, P, SZ, I], I),
         "gw_polarization": ([P, P, P, I, I, P], I),
         "gw_set_hermitian": ([P, I], I),
+        "gw_set_mu_window": ([P, D], I),
         "gw_hermitize": ([P, P, I, LL], I),
         "gw_tau_to_iw": ([P, I, P, LL, LL, P], I),
         "gw_iw_to_tau": ([P, I, P, LL, LL, P], I),
@@ -236,6 +237,12 @@ def gw_set_hermitian(ctx, on, two_slot=False):
     gw_polarization2 (see gw.h)."""
     mode = (GW_HERM_FORWARD if on else 0) | (GW_HERM_TWO_SLOT if two_slot else 0)
     ctx._check(load().gw_set_hermitian(ctx.h, mode), "gw_set_hermitian")
+
+
+def gw_set_mu_window(ctx, ne_tol):
+    """gw_find_mu returns the midpoint of the mu interval where
+    |N_e - n_target| <= ne_tol (0: the root; see gw.h)."""
+    ctx._check(load().gw_set_mu_window(ctx.h, float(ne_tol)), "gw_set_mu_window")
 
 
 def gw_hermitize(ctx, X, n):

@@ -248,6 +248,36 @@ def test_find_mu(small, with_sigma):
     assert np.abs(host(Gt) - ogw.to_tau(g.TFp, Giw_r)).max() < TOL
 
 
+def test_find_mu_window(small):
+    """gw_set_mu_window: the given mu when its count is within the window,
+    else the midpoint of the mu interval where it is, as in the oracle (the
+    same decision on both sides); 0 restores the root."""
+    from paper_2206_07660_amd import gw
+    c, g, wl = small["ctx"], small["g"], small["wl"]
+    sinf, siw = _random_sigma(c, g, 7)
+    Giw = torch.empty(c.giw_shape(), dtype=torch.complex128, device="cuda")
+    Gt = torch.empty(c.g_shape(), dtype=torch.complex128, device="cuda")
+    try:
+        kept = []
+        for w, mu0 in ((1e-9, 0.0), (1e-3, 0.0), (0.5, 0.0), (0.5, 0.3)):
+            gw.gw_set_mu_window(c, w)
+            mu, n = gw.gw_find_mu(c, small["dH0"], small["dS"], dev(sinf), dev(siw), wl.n_target, mu0,
+                                  G_iw=Giw, G_tau=Gt)
+            mu_o, Giw_o, n_o = ogw.find_mu(small["H0"], small["S"], sinf, siw, wl.n_target, g, NS, mu0,
+                                           window=w)
+            print("mu window", w, mu0, mu, mu_o, n, n_o)
+            kept.append(mu == mu0)
+            assert (mu == mu0) == (mu_o == mu0)
+            assert abs(mu - mu_o) < 1e-10
+            assert abs(n - wl.n_target) <= w + 1e-12
+            assert np.abs(host(Gt) - ogw.to_tau(g.TFp, Giw_o)).max() < TOL
+        assert not kept[0] and kept[2]        # searched from outside, kept inside
+        with pytest.raises(gw.GwError):
+            gw.gw_set_mu_window(c, -1.0)
+    finally:
+        gw.gw_set_mu_window(c, 0.0)
+
+
 def test_sigma_evaluation_chain(small):
     from paper_2206_07660_amd.scgw import GWPath
     c, g, wl = small["ctx"], small["g"], small["wl"]

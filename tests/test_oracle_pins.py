@@ -117,6 +117,55 @@ def test_noninteracting_electron_count_and_mu():
     assert np.abs(gw.to_tau(g.TFp, Giw) - G0).max() < 1e-11
 
 
+def _gapped(nk=2, beta=50.0, ntau=100, seed=9):
+    """H0^k = U_k diag(-0.8, -0.6, -0.6, 0.5) U_k^dagger (a 1.1 Ha gap, the
+    occupied edge twice degenerate), S = I."""
+    rng = np.random.default_rng(seed)
+    eps = np.array([-0.8, -0.6, -0.6, 0.5])
+    H0 = np.empty((nk, 4, 4), complex)
+    for k in range(nk):
+        q, r = np.linalg.qr(rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4)))
+        H0[k] = (q * eps) @ q.conj().T
+    S = np.broadcast_to(np.eye(4, dtype=complex), (nk, 4, 4)).copy()
+    return H0, S, eps, og.Grids(beta, ntau)
+
+
+def test_mu_window_midpoint_noninteracting():
+    """window: from a start outside it, mu is the midpoint of the interval where the closed-form count
+    (ns/Nk) sum f(eps - mu) is within the window of the target (roots found
+    by brentq on the exact Fermi sum).  Mid-gap the exact count differs from
+    the target by far less than the grid count's representation error, so
+    the root of the grid count is far from the exact root while the window
+    midpoint is not."""
+    from scipy.optimize import brentq
+    beta = 50.0
+    H0, S, eps, g = _gapped(beta=beta)
+    nk = H0.shape[0]
+    z = np.zeros((nk, 4, 4), complex)
+    zw = np.zeros((g.wF.size, nk, 4, 4), complex)
+
+    def n_exact(mu):
+        return NS * np.sum(1.0 / (1.0 + np.exp(beta * (eps - mu))))
+
+    target, w = 6.0, 1e-6
+    lo = brentq(lambda m: n_exact(m) - (target - w), -0.6, 0.5, xtol=1e-15)
+    hi = brentq(lambda m: n_exact(m) - (target + w), -0.6, 0.5, xtol=1e-15)
+    root = brentq(lambda m: n_exact(m) - target, -0.6, 0.5, xtol=1e-15)
+    assert abs(n_exact(0.35) - target) > 1e-4              # a start outside the window
+    mu, Giw, n = gw.find_mu(H0, S, z, zw, target, g, NS, 0.35, window=w)
+    mu_root, _, _ = gw.find_mu(H0, S, z, zw, target, g, NS, 0.35)
+    print("window midpoint", mu, 0.5 * (lo + hi), "root", mu_root, root)
+    # the grid count's representation error (about 2e-10 here) moves the
+    # window edges by about that over the slope beta * w
+    assert abs(mu - 0.5 * (lo + hi)) < 1e-4
+    assert abs(mu_root - root) > 100 * abs(mu - 0.5 * (lo + hi))
+    assert abs(n - target) <= w
+    # a start inside the window is kept as it is
+    for mu0 in (0.0, -0.2):
+        assert abs(n_exact(mu0) - target) < 1e-7
+        assert gw.find_mu(H0, S, z, zw, target, g, NS, mu0, window=w)[0] == mu0
+
+
 # ------------------------------------------------ brute force (tiny sizes) ---
 def test_bruteforce_polarization_selfenergy_hf():
     wl, g, H0, S, V, G = _setup()
