@@ -242,6 +242,19 @@ gw_status gw_find_mu(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig
  * A negative or non-finite ne_tol is GW_ERR_ARG.                            */
 gw_status gw_set_mu_window(gw_ctx* ctx, double ne_tol);
 
+/* Finite-size corrections of Eqs. K_corr and GW_head_corr (Sec. III.D),
+ * added in place:
+ *   Sig_inf^k           += -chi S^k gamma^k S^k
+ *   Sig_tau^k(tau_i)    += -chi head[i] S^k G^k(tau_i) S^k
+ * chi is the supercell Madelung constant and head[i] (host, ntau doubles) is
+ * eps^{-1}_{00}(-tau_i) - 1, the head of the inverse dielectric function at
+ * q = 0 minus one; both are inputs (the paper fits eps from q-points near
+ * Gamma of a real crystal).  S, gamma, Sig_inf are [k][i][j]; G_tau, Sig_tau
+ * [tau][k][i][j].  gamma with Sig_inf and G_tau with head and Sig_tau may
+ * each be NULL to skip that term.  Needs nao <= 64; either precision.       */
+gw_status gw_finite_size(gw_ctx* ctx, const gw_z* S, double chi, const gw_z* gamma, gw_z* Sig_inf,
+                         const gw_z* G_tau, const double* head, gw_z* Sig_tau);
+
 /* Damped update and convergence measure of the scGW loop (Sec. IV.A):
  * Y <- (1 - alpha) Y + alpha X_new over n complex elements.  X_new may be
  * NULL, in which case Y <- (1 - alpha) Y, and alpha = 1 writes zeros without

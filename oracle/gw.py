@@ -227,6 +227,20 @@ def find_mu(H0, S, Sig_inf, Sig_iw, n_target, grids, ns, mu0=0.0, tol=1e-13, max
     return mu, G_iw, count_from_iw(G_iw, S, grids, ns)
 
 
+# ------------------------------------------------ finite-size corrections ---
+def finite_size_corrections(S, gamma, G_tau, chi, head):
+    """Eq. K_corr: Delta_HF^k = -chi S^k gamma^k S^k, and Eq. GW_head_corr:
+    Delta_GW^k(tau_i) = -chi head[i] S^k G^k(tau_i) S^k with head[i] =
+    eps^{-1}_{00}(-tau_i) - 1 (Sec. III.D; chi and the dielectric head are
+    inputs)."""
+    d_hf = np.stack([-chi * S[k] @ gamma[k] @ S[k] for k in range(S.shape[0])])
+    d_gw = np.empty_like(G_tau)
+    for i in range(G_tau.shape[0]):
+        for k in range(S.shape[0]):
+            d_gw[i, k] = -chi * head[i] * (S[k] @ G_tau[i, k] @ S[k])
+    return d_hf, d_gw
+
+
 # ----------------------------------------- one Sigma[G] + Pi evaluation ------
 def sigma_evaluation(V, G_tau, grids, mesh, ns):
     """Sigma_inf[G] and Sigma~[G](tau): Eqs. HF_J/HF_K and the chain

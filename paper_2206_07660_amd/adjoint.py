@@ -29,6 +29,8 @@ class SigmaDerivatives:
     or recomputes it per q inside each derivative call (per_q=True)."""
 
     def __init__(self, path, per_q=False):
+        if getattr(path, "finite_size", None) is not None:
+            raise NotImplementedError("the derivatives do not include the finite-size corrections")
         self.path = path
         self.ctx = path.ctx
         self.per_q = per_q

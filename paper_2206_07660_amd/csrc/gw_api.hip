@@ -1369,6 +1369,35 @@ gw_status gw_hermitize(gw_ctx* c, gw_z* X, int n, long long nmat) {
   return GW_OK;
 }
 
+// ------------------------------------------------- finite-size corrections
+gw_status gw_finite_size(gw_ctx* c, const gw_z* S, double chi, const gw_z* gamma, gw_z* Sig_inf,
+                         const gw_z* G_tau, const double* head, gw_z* Sig_tau) {
+  if (!c) return GW_ERR_ARG;
+  const int nao = c->d.nao, nk = c->nk, nt = c->d.ntau;
+  if (nao > 64) return fail(c, GW_ERR_ARG, "gw_finite_size needs nao <= 64");
+  if (!std::isfinite(chi)) return fail(c, GW_ERR_ARG, "chi is not finite");
+  if (!S) return fail(c, GW_ERR_ARG, "NULL S");
+  if (!gamma != !Sig_inf) return fail(c, GW_ERR_ARG, "gamma and Sig_inf go together");
+  if (!G_tau != !Sig_tau || (G_tau && !head))
+    return fail(c, GW_ERR_ARG, "G_tau, head and Sig_tau go together");
+  if (head)
+    for (int i = 0; i < nt; ++i)
+      if (!std::isfinite(head[i])) return fail(c, GW_ERR_ARG, "head is not finite");
+  if (gamma)
+    HIPCHK(c, sxs_add_launch((const double2*)S, (const double2*)gamma, (double2*)Sig_inf, nao, nk, nk,
+                             -chi, c->st));
+  if (G_tau) {
+    // Sigma~(tau_i) += -chi head_i S G(tau_i) S: one launch per tau node
+    const size_t slab = (size_t)nk * c->n2;
+    for (int i = 0; i < nt; ++i) {
+      if (head[i] == 0.0) continue;
+      HIPCHK(c, sxs_add_launch((const double2*)S, (const double2*)G_tau + i * slab,
+                               (double2*)Sig_tau + i * slab, nao, nk, nk, -chi * head[i], c->st));
+    }
+  }
+  return GW_OK;
+}
+
 // ---------------------------------------------------------------- Dyson JVP
 gw_status gw_dyson_jvp(gw_ctx* c, const gw_z* S, const gw_z* G_iw, const gw_z* dSinf,
                        const gw_z* dSig_iw, int fixed_mu, gw_z* dG_iw, double* dmu) {

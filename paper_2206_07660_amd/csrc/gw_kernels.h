@@ -122,5 +122,9 @@ hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, i
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st);
 // P[b] <- (P[b] + P[b]^H) / 2 for b < nmat (n x n, row-major).
 hipError_t herm_avg_launch(double2* P, int n, long long nmat, hipStream_t st);
+// Finite-size corrections: Out[b] += alpha S[b % nk] X[b] S[b % nk] for
+// b < nmat (nk S matrices, nmat X and Out matrices, all n x n, n <= 64).
+hipError_t sxs_add_launch(const double2* S, const double2* X, double2* Out, int n, int nk,
+                          long long nmat, double alpha, hipStream_t st);
 hipError_t wlu_launch(int which, const double2* P0, double2* A, double2* B, int n, int j0, int nb,
                       long long nmat, int* flag, hipStream_t st);

@@ -758,6 +758,50 @@ hipError_t herm_avg_launch(double2* P, int n, long long nmat, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Finite-size corrections (Eqs. K_corr, GW_head_corr): one workgroup per
+// matrix b.  T = X[b] S[k] is formed in LDS (one thread per entry, a row of
+// X times a column of S), then every thread adds alpha (S[k] T)(i, j) for its
+// entries.  n <= 64, so T fits in 64 KiB of LDS.
+__global__ void __launch_bounds__(256) sxs_add_k(const double2* S, const double2* X, double2* Out,
+                                                 int n, int nk, double alpha) {
+  __shared__ double2 T[64 * 64];
+  const unsigned nn = (unsigned)n * (unsigned)n;
+  const unsigned b = blockIdx.x;
+  const double2* Sk = S + (size_t)(b % (unsigned)nk) * nn;
+  const double2* Xb = X + (size_t)b * nn;
+  for (unsigned e = threadIdx.x; e < nn; e += 256u) {
+    const unsigned r = e / (unsigned)n, c = e - r * (unsigned)n;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double2 x = Xb[(size_t)r * n + a], s = Sk[(size_t)a * n + c];
+      re += x.x * s.x - x.y * s.y;
+      im += x.x * s.y + x.y * s.x;
+    }
+    T[e] = double2{re, im};
+  }
+  __syncthreads();
+  double2* Ob = Out + (size_t)b * nn;
+  for (unsigned e = threadIdx.x; e < nn; e += 256u) {
+    const unsigned r = e / (unsigned)n, c = e - r * (unsigned)n;
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double2 s = Sk[(size_t)r * n + a], x = T[(unsigned)a * (unsigned)n + c];
+      re += s.x * x.x - s.y * x.y;
+      im += s.x * x.y + s.y * x.x;
+    }
+    const double2 o = Ob[e];
+    Ob[e] = double2{o.x + alpha * re, o.y + alpha * im};
+  }
+}
+
+hipError_t sxs_add_launch(const double2* S, const double2* X, double2* Out, int n, int nk,
+                          long long nmat, double alpha, hipStream_t st) {
+  if (n <= 0 || nmat <= 0) return hipSuccess;
+  if (n > 64 || nk <= 0 || nmat > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  sxs_add_k<<<dim3((unsigned)nmat, 1, 1), 256, 0, st>>>(S, X, Out, n, nk, alpha);
+  return hipGetLastError();
+}
+
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st) {
   if (n <= 0 || nmat <= 0) return hipSuccess;
   if (nmat > 65535 || (long long)n * n > 0x7fffffffLL) return hipErrorInvalidConfiguration;

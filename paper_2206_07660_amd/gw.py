@@ -29,7 +29,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
            "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
-           "gw_hermitize", "gw_set_mu_window"]
+           "gw_hermitize", "gw_set_mu_window", "gw_finite_size"]
 
 
 class GwError(RuntimeError):
@@ -66,6 +66,7 @@ def load():
         "gw_polarization": ([P, P, P, I, I, P], I),
         "gw_set_hermitian": ([P, I], I),
         "gw_set_mu_window": ([P, D], I),
+        "gw_finite_size": ([P, P, D, P, P, P, P, P], I),
         "gw_hermitize": ([P, P, I, LL], I),
         "gw_tau_to_iw": ([P, I, P, LL, LL, P], I),
         "gw_iw_to_tau": ([P, I, P, LL, LL, P], I),
@@ -243,6 +244,22 @@ def gw_set_mu_window(ctx, ne_tol):
     """gw_find_mu returns the midpoint of the mu interval where
     |N_e - n_target| <= ne_tol (0: the root; see gw.h)."""
     ctx._check(load().gw_set_mu_window(ctx.h, float(ne_tol)), "gw_set_mu_window")
+
+
+def gw_finite_size(ctx, S, chi, gamma=None, Sig_inf=None, G_tau=None, head=None, Sig_tau=None):
+    """Sig_inf += -chi S gamma S and Sig_tau(tau_i) += -chi head[i] S G(tau_i) S
+    (head: ntau values of eps^{-1}_00(-tau_i) - 1, host); see gw.h."""
+    hp = None
+    if head is not None:
+        h = np.ascontiguousarray(np.asarray(head, dtype=np.float64))
+        if h.shape != (ctx.ntau,):
+            raise ValueError("head must hold ntau values")
+        hp = h.ctypes.data_as(ctypes.c_void_p)
+    ks, gs = ctx.k_shape(), ctx.g_shape()
+    ctx._check(load().gw_finite_size(ctx.h, _ptr(S, "S", ks), float(chi), _ptr(gamma, "gamma", ks),
+                                     _ptr(Sig_inf, "Sig_inf", ks), _ptr(G_tau, "G_tau", gs), hp,
+                                     _ptr(Sig_tau, "Sig_tau", gs)),
+               "gw_finite_size")
 
 
 def gw_hermitize(ctx, X, n):

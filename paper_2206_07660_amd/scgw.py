@@ -31,10 +31,15 @@ class State:
 class GWPath:
     """hermitian: every G given to sigma() is Hermitian per (tau, k), as any
     Green's function of Hermitian H0, S and Sigma is, and V has the pair
-    relation; gw_polarization then contracts only half of each P0 matrix."""
+    relation; gw_polarization then contracts only half of each P0 matrix.
+    finite_size: None, or (chi, head) with the Madelung constant chi and the
+    ntau values head[i] = eps^{-1}_00(-tau_i) - 1; sigma() then adds the
+    corrections of Eqs. K_corr and GW_head_corr (gw_finite_size)."""
 
-    def __init__(self, ctx: gw.Context, V, H0, S, n_target, alpha=0.5, hermitian=True):
+    def __init__(self, ctx: gw.Context, V, H0, S, n_target, alpha=0.5, hermitian=True,
+                 finite_size=None):
         self.ctx, self.V, self.H0, self.S = ctx, V, H0, S
+        self.finite_size = None if finite_size is None else (float(finite_size[0]), finite_size[1])
         self.hermitian = bool(hermitian)
         gw.gw_set_hermitian(ctx, self.hermitian)
         self.n_target, self.alpha = float(n_target), float(alpha)
@@ -63,6 +68,9 @@ class GWPath:
         gw.gw_iw_to_tau(c, gw.GW_BOSON, self.Pw, self.P0, batch=c.nk)
         gw.gw_mix(c, 1.0, None, out_tau)                     # zero before accumulating
         gw.gw_self_energy(c, self.V, G_tau, self.P0, 0, c.nk, out_tau)
+        if self.finite_size is not None:
+            chi, head = self.finite_size
+            gw.gw_finite_size(c, self.S, chi, self.gamma, out_inf, G_tau, head, out_tau)
         return out_inf, out_tau
 
     # ------------------------------------------------ scGW loop -----------

@@ -278,6 +278,61 @@ def test_find_mu_window(small):
         gw.gw_set_mu_window(c, 0.0)
 
 
+def test_finite_size_corrections(small):
+    """gw_finite_size (Eqs. K_corr, GW_head_corr) against the oracle, added in
+    place onto existing self-energies, with each term alone and with a
+    non-orthogonal S; argument errors leave the outputs untouched."""
+    from paper_2206_07660_amd import gw
+    c, g, wl = small["ctx"], small["g"], small["wl"]
+    rng = np.random.default_rng(41)
+    gam = inp.circular_gaussian(rng, c.k_shape(), 0.3)
+    base_inf = inp.circular_gaussian(rng, c.k_shape(), 0.2)
+    base_tau = inp.circular_gaussian(rng, c.g_shape(), 0.2)
+    head = -0.3 * (np.exp(-0.7 * g.tau) + np.exp(-0.7 * (wl.beta - g.tau)))
+    B = inp.circular_gaussian(rng, c.k_shape(), 0.1)
+    S = np.eye(c.nao) + B + np.conj(np.swapaxes(B, -1, -2))        # Hermitian, not orthogonal
+    chi = 0.29
+    r_hf, r_gw = ogw.finite_size_corrections(S, gam, small["G"], chi, head)
+    si, st = dev(base_inf), dev(base_tau)
+    gw.gw_finite_size(c, dev(S), chi, dev(gam), si, small["dG"], head, st)
+    e1 = np.abs(host(si) - (base_inf + r_hf)).max()
+    e2 = np.abs(host(st) - (base_tau + r_gw)).max()
+    print("finite-size corrections max err", e1, e2)
+    assert e1 < TOL and e2 < TOL
+    # each term alone
+    si, st = dev(base_inf), dev(base_tau)
+    gw.gw_finite_size(c, dev(S), chi, gamma=dev(gam), Sig_inf=si)
+    gw.gw_finite_size(c, dev(S), chi, G_tau=small["dG"], head=head, Sig_tau=st)
+    assert np.abs(host(si) - (base_inf + r_hf)).max() < TOL
+    assert np.abs(host(st) - (base_tau + r_gw)).max() < TOL
+    # argument errors are found before anything is written
+    st = dev(base_tau)
+    with pytest.raises(gw.GwError):
+        gw.gw_finite_size(c, small["dS"], chi, G_tau=small["dG"], head=np.full(wl.ntau, np.nan), Sig_tau=st)
+    with pytest.raises(gw.GwError):
+        gw.gw_finite_size(c, small["dS"], float("inf"), gamma=dev(gam), Sig_inf=dev(base_inf))
+    assert np.array_equal(host(st), base_tau)
+
+
+def test_sigma_chain_with_finite_size_corrections(small):
+    """GWPath(finite_size=(chi, head)): the Sigma evaluation plus both
+    corrections, with gamma of the same G, against the oracle."""
+    from paper_2206_07660_amd.scgw import GWPath
+    c, g, wl = small["ctx"], small["g"], small["wl"]
+    head = -0.3 * (np.exp(-0.7 * g.tau) + np.exp(-0.7 * (wl.beta - g.tau)))
+    path = GWPath(c, small["dV"], small["dH0"], small["dS"], wl.n_target, finite_size=(0.29, head))
+    sinf, stau = path.sigma(small["dG"])
+    r_inf, r_tau, d = ogw.sigma_evaluation(small["V"], small["G"], g, wl.mesh, NS)
+    c_hf, c_gw = ogw.finite_size_corrections(small["S"], d["gamma"], small["G"], 0.29, head)
+    e1 = np.abs(host(sinf) - (r_inf + c_hf)).max()
+    e2 = np.abs(host(stau) - (r_tau + c_gw)).max()
+    print("chain with corrections", e1, e2, np.abs(c_hf).max(), np.abs(c_gw).max())
+    assert e1 < TOL and e2 < TOL and np.abs(c_hf).max() > 1e-2
+    from paper_2206_07660_amd.adjoint import SigmaDerivatives
+    with pytest.raises(NotImplementedError):
+        SigmaDerivatives(path)
+
+
 def test_sigma_evaluation_chain(small):
     from paper_2206_07660_amd.scgw import GWPath
     c, g, wl = small["ctx"], small["g"], small["wl"]

@@ -166,6 +166,48 @@ def test_mu_window_midpoint_noninteracting():
         assert gw.find_mu(H0, S, z, zw, target, g, NS, mu0, window=w)[0] == mu0
 
 
+def _s_eigen(H0, S, mu):
+    """S-orthonormal eigenvectors C (C^dagger S C = I) and xi = eps - mu per k."""
+    out = []
+    for k in range(H0.shape[0]):
+        e, C = sla.eigh(H0[k], S[k])
+        out.append((e - mu, C))
+    return out
+
+
+def test_finite_size_hf_shifts_occupations():
+    """Eq. K_corr with gamma = C diag(f) C^dagger (closed form): the generalised
+    eigenvalues of (H0 + Delta_HF, S) are eps_a - chi f_a, since
+    (H0 - chi S gamma S) C = S C (diag(eps) - chi diag(f))."""
+    wl, g, H0, S, V, G = _setup(nao=5, beta=8.0, ntau=10, s_kind="overlap")
+    mu, chi = 0.1, 0.37
+    gam = np.empty_like(H0)
+    want = []
+    for k, (xi, C) in enumerate(_s_eigen(H0, S, mu)):
+        f = 1.0 / (1.0 + np.exp(wl.beta * xi))
+        gam[k] = (C * f) @ C.conj().T
+        want.append(np.sort(xi + mu - chi * f))
+    d_hf, _ = gw.finite_size_corrections(S, gam, G, chi, np.zeros(wl.ntau))
+    for k in range(wl.nk):
+        got = sla.eigh(H0[k] + d_hf[k], S[k], eigvals_only=True)
+        assert np.abs(np.sort(got) - want[k]).max() < 1e-12
+
+
+def test_finite_size_head_is_diagonal_in_the_eigenbasis():
+    """Eq. GW_head_corr at G = G0 (closed form): C^dagger Delta_GW(tau) C =
+    chi head(tau) diag(g_a(tau)), g_a(tau) = exp(-xi_a tau) / (1 + exp(-beta xi_a)),
+    because G0 = -C diag(g) C^dagger and C^dagger S C = I."""
+    wl, g, H0, S, V, G = _setup(nao=5, beta=8.0, ntau=10, s_kind="overlap")
+    mu, chi = 0.1, 0.37
+    head = -0.4 * (np.exp(-0.9 * g.tau) + np.exp(-0.9 * (wl.beta - g.tau)))
+    _, d_gw = gw.finite_size_corrections(S, np.zeros_like(H0), G, chi, head)
+    for k, (xi, C) in enumerate(_s_eigen(H0, S, mu)):
+        for i, tau in enumerate(g.tau):
+            ga = np.exp(-xi * tau) / (1.0 + np.exp(-wl.beta * xi))
+            M = C.conj().T @ d_gw[i, k] @ C
+            assert np.abs(M - np.diag(chi * head[i] * ga)).max() < 1e-12
+
+
 # ------------------------------------------------ brute force (tiny sizes) ---
 def test_bruteforce_polarization_selfenergy_hf():
     wl, g, H0, S, V, G = _setup()
