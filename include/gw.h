@@ -185,6 +185,19 @@ gw_status gw_iw_to_tau(gw_ctx* ctx, int stat, const gw_z* X_iw, long long batch,
  * returns GW_ERR_SINGULAR (the outputs are then undefined).                  */
 gw_status gw_screened_W(gw_ctx* ctx, const gw_z* P0_iw, int nq, gw_z* Pt_iw);
 
+/* gw_screened_W plus the dynamical Luttinger-Ward term of the same
+ * factorisation, Eq. tilde_Phi_GW:
+ *   *phi = (1/(2 Nk)) sum_{q < nq} (1/beta) sum_n tr{ln[I - P0^q(i W_n)] + P0^q(i W_n)}
+ * (host double; the q given are the first nq of the P0_iw array, so q ranges
+ * add up).  Phi is real and F(-iW) = conj F(iW) on the symmetric sparse sets,
+ * so only Re F = ln|det(I - P0)| + Re tr P0 enters, with ln|det| from the
+ * diagonal of U.  The sum over all bosonic frequencies is the value at tau = 0
+ * of the bosonic function whose transform is F: the least-squares fit on the
+ * tau nodes evaluated at tau = 0 (weights: the beta^- row reversed, by the
+ * mirrored nodes, times the inverse bosonic transform, real part).
+ * Synchronises; errors as gw_screened_W (then *phi = 0).                  */
+gw_status gw_screened_W_phi(gw_ctx* ctx, const gw_z* P0_iw, int nq, gw_z* Pt_iw, double* phi);
+
 /* Eq. tilde_sigma2, ACCUMULATED over q = q0 .. q0+nq-1 (Pt_tau[q-q0] holds
  * P~^q(tau)):
  *   Sig_tau^k_{ij}(tau) += -(1/Nk) sum_q sum_{ab} sum_{QQ'} G^{k-q}_{ab}(tau)

@@ -241,6 +241,25 @@ def finite_size_corrections(S, gamma, G_tau, chi, head):
     return d_hf, d_gw
 
 
+# --------------------------------------------------- Luttinger-Ward part ---
+def phi_gw(P0w, grids, nk):
+    """Eq. tilde_Phi_GW: (1/(2 Nk)) sum_q (1/beta) sum_n tr{ln[I - P0^q(i W_n)]
+    + P0^q(i W_n)} over all bosonic frequencies.  Phi is real and F(-iW) is the
+    conjugate of F(iW), so only Re F = ln|det(I - P0)| + Re tr P0 enters.  The
+    Matsubara sum (1/beta) sum_n F(iW_n) is the value at tau = 0 of the bosonic
+    function whose transform F is; on the sparse set it is read off the
+    least-squares fit TBp and the interpolant's value at tau = 0, which by the
+    mirrored nodes is the beta^- row reversed: weights Re(w[::-1] @ TBp)."""
+    cw = np.real(grids.w[::-1] @ grids.TBp)
+    total = 0.0
+    for q in range(P0w.shape[0]):
+        for n in range(P0w.shape[1]):
+            P = P0w[q, n]
+            sign, logdet = np.linalg.slogdet(np.eye(P.shape[0]) - P)
+            total += cw[n] * (logdet + np.trace(P).real)
+    return total / (2.0 * nk)
+
+
 # ----------------------------------------- one Sigma[G] + Pi evaluation ------
 def sigma_evaluation(V, G_tau, grids, mesh, ns):
     """Sigma_inf[G] and Sigma~[G](tau): Eqs. HF_J/HF_K and the chain

@@ -746,6 +746,33 @@ gw_status gw_screened_W(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt) {
   return read_flag(c, "screened_W");
 }
 
+// ------------------------------------------------------ Eq. tilde_Phi_GW
+gw_status gw_screened_W_phi(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt, double* phi) {
+  if (!c) return GW_ERR_ARG;
+  if (!phi) return fail(c, GW_ERR_ARG, "NULL phi");
+  *phi = 0.0;
+  gw_status s = gw_screened_W(c, P0, nq, Pt);
+  if (s != GW_OK || nq == 0) return s;
+  // The LU of I - P0 is still packed in the workspace.  Weights of the
+  // Matsubara sum: value at tau = 0 of the least-squares fit, i.e. the
+  // beta^- row reversed (mirrored nodes) times TBp; real part, scaled by
+  // 1 / (2 Nk).  dred[0] is the accumulator, dred[1..nw_b] the weights.
+  const int nt = c->d.ntau, nwb = c->d.nw_b;
+  if (nwb + 1 > 2 * 1024 + 8) return fail(c, GW_ERR_ARG, "gw_screened_W_phi supports nw_b <= 2055");
+  std::vector<double> up((size_t)nwb + 1, 0.0);
+  for (int n = 0; n < nwb; ++n) {
+    double r = 0.0;
+    for (int i = 0; i < nt; ++i) r += c->w[nt - 1 - i] * c->TBp[(size_t)i * nwb + n].real();
+    up[1 + n] = r / (2.0 * c->nk);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->dred, up.data(), up.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, phi_terms_launch((const double2*)c->ws, (const double2*)P0, c->d.naux,
+                             (long long)nq * nwb, c->dred + 1, nwb, c->dred, c->st));
+  HIPCHK(c, hipMemcpyAsync(phi, c->dred, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return GW_OK;
+}
+
 // ------------------------------------------------------------- Eq. tilde_sigma2
 gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt, int q0, int nq,
                          gw_z* Sig) {

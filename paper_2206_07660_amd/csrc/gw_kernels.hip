@@ -802,6 +802,31 @@ hipError_t sxs_add_launch(const double2* S, const double2* X, double2* Out, int 
   return hipGetLastError();
 }
 
+// Eq. tilde_Phi_GW: one wave per matrix; lanes stride over the diagonal,
+// a butterfly reduction sums the wave, lane 0 adds the weighted term.
+__global__ void __launch_bounds__(64) phi_terms_k(const double2* LU, const double2* P0, int n,
+                                                  const double* wts, int nw, double* acc) {
+  const size_t m = blockIdx.x;
+  const size_t nn = (size_t)n * (size_t)n;
+  const double2* A = LU + m * nn;
+  const double2* P = P0 + m * nn;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) {
+    const double2 u = A[(size_t)i * n + i];
+    s += log(hypot(u.x, u.y)) + P[(size_t)i * n + i].x;
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) atomicAdd(acc, wts[m % (size_t)nw] * s);
+}
+
+hipError_t phi_terms_launch(const double2* LU, const double2* P0, int n, long long nmat,
+                            const double* wts, int nw, double* acc, hipStream_t st) {
+  if (n <= 0 || nmat <= 0) return hipSuccess;
+  if (nw <= 0 || nmat > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  phi_terms_k<<<dim3((unsigned)nmat, 1, 1), 64, 0, st>>>(LU, P0, n, wts, nw, acc);
+  return hipGetLastError();
+}
+
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st) {
   if (n <= 0 || nmat <= 0) return hipSuccess;
   if (nmat > 65535 || (long long)n * n > 0x7fffffffLL) return hipErrorInvalidConfiguration;

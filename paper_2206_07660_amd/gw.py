@@ -29,7 +29,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
            "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
-           "gw_hermitize", "gw_set_mu_window", "gw_finite_size"]
+           "gw_hermitize", "gw_set_mu_window", "gw_finite_size", "gw_screened_W_phi"]
 
 
 class GwError(RuntimeError):
@@ -67,6 +67,7 @@ def load():
         "gw_set_hermitian": ([P, I], I),
         "gw_set_mu_window": ([P, D], I),
         "gw_finite_size": ([P, P, D, P, P, P, P, P], I),
+        "gw_screened_W_phi": ([P, P, I, P, P], I),
         "gw_hermitize": ([P, P, I, LL], I),
         "gw_tau_to_iw": ([P, I, P, LL, LL, P], I),
         "gw_iw_to_tau": ([P, I, P, LL, LL, P], I),
@@ -319,6 +320,16 @@ def gw_screened_W(ctx, P0_iw, Pt_iw):
     shp = (nq, ctx.nw_b, ctx.naux, ctx.naux)
     ctx._check(load().gw_screened_W(ctx.h, _ptr(P0_iw, "P0_iw", shp), nq, _ptr(Pt_iw, "Pt_iw", shp)),
                "gw_screened_W")
+
+
+def gw_screened_W_phi(ctx, P0_iw, Pt_iw):
+    """gw_screened_W plus Eq. tilde_Phi_GW over the nq q-points given; returns Phi~."""
+    nq = int(P0_iw.shape[0])
+    shp = (nq, ctx.nw_b, ctx.naux, ctx.naux)
+    out = ctypes.c_double(0.0)
+    ctx._check(load().gw_screened_W_phi(ctx.h, _ptr(P0_iw, "P0_iw", shp), nq, _ptr(Pt_iw, "Pt_iw", shp),
+                                        ctypes.byref(out)), "gw_screened_W_phi")
+    return out.value
 
 
 def gw_self_energy(ctx, V, G_tau, Pt_tau, q0, nq, Sig_tau):

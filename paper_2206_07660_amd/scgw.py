@@ -37,8 +37,11 @@ class GWPath:
     corrections of Eqs. K_corr and GW_head_corr (gw_finite_size)."""
 
     def __init__(self, ctx: gw.Context, V, H0, S, n_target, alpha=0.5, hermitian=True,
-                 finite_size=None):
+                 finite_size=None, want_phi=False):
         self.ctx, self.V, self.H0, self.S = ctx, V, H0, S
+        # want_phi: sigma() takes the screened-interaction solve through
+        # gw_screened_W_phi and keeps Phi~ (Eq. tilde_Phi_GW) of that G in self.phi
+        self.want_phi, self.phi = bool(want_phi), float("nan")
         self.finite_size = None if finite_size is None else (float(finite_size[0]), finite_size[1])
         self.hermitian = bool(hermitian)
         gw.gw_set_hermitian(ctx, self.hermitian)
@@ -64,7 +67,10 @@ class GWPath:
         gw.gw_set_hermitian(c, self.hermitian)         # the context may be shared
         gw.gw_polarization(c, self.V, G_tau, 0, c.nk, self.P0)
         gw.gw_tau_to_iw(c, gw.GW_BOSON, self.P0, self.P0w, batch=c.nk)
-        gw.gw_screened_W(c, self.P0w, self.Pw)
+        if self.want_phi:
+            self.phi = gw.gw_screened_W_phi(c, self.P0w, self.Pw)
+        else:
+            gw.gw_screened_W(c, self.P0w, self.Pw)
         gw.gw_iw_to_tau(c, gw.GW_BOSON, self.Pw, self.P0, batch=c.nk)
         gw.gw_mix(c, 1.0, None, out_tau)                     # zero before accumulating
         gw.gw_self_energy(c, self.V, G_tau, self.P0, 0, c.nk, out_tau)

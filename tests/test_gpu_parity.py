@@ -333,6 +333,33 @@ def test_sigma_chain_with_finite_size_corrections(small):
         SigmaDerivatives(path)
 
 
+def test_screened_W_phi(small):
+    """gw_screened_W_phi: the same P~ as gw_screened_W and Eq. tilde_Phi_GW as
+    the oracle (slogdet on the CPU vs the LU diagonal on the GPU); q ranges add."""
+    from paper_2206_07660_amd import gw
+    c, g, wl = small["ctx"], small["g"], small["wl"]
+    _, _, d = ogw.sigma_evaluation(small["V"], small["G"], g, wl.mesh, NS)
+    P0w = dev(d["P0w"])
+    Pt = torch.empty_like(P0w)
+    Pt2 = torch.empty_like(P0w)
+    phi = gw.gw_screened_W_phi(c, P0w, Pt)
+    gw.gw_screened_W(c, P0w, Pt2)
+    ref = ogw.phi_gw(d["P0w"], g, wl.nk)
+    print("Phi~", phi, ref, "rel", abs(phi - ref) / abs(ref))
+    assert torch.equal(Pt, Pt2)
+    # the weights come from grid tables built independently on each side
+    # (agreeing to 1e-13 .. 1e-11), so the fp64 bound of the path applies
+    assert abs(phi - ref) < TOL * max(1.0, abs(ref)) and abs(ref) > 1e-6
+    a = gw.gw_screened_W_phi(c, P0w[:3].contiguous(), Pt[:3].contiguous())
+    b = gw.gw_screened_W_phi(c, P0w[3:].contiguous(), Pt[3:].contiguous())
+    assert abs(a + b - phi) < 1e-13 * max(1.0, abs(phi))
+    # the scGW path keeps Phi~ of the G it evaluates
+    from paper_2206_07660_amd.scgw import GWPath
+    path = GWPath(c, small["dV"], small["dH0"], small["dS"], wl.n_target, want_phi=True)
+    path.sigma(small["dG"])
+    assert abs(path.phi - ref) < TOL * max(1.0, abs(ref))
+
+
 def test_sigma_evaluation_chain(small):
     from paper_2206_07660_amd.scgw import GWPath
     c, g, wl = small["ctx"], small["g"], small["wl"]

@@ -267,6 +267,34 @@ def test_scalar_chain_closed_form(eps, mu, v):
     gamma = d["gamma"][0, 0, 0]
     assert abs(gamma - f) < 1e-12
     assert abs(sinf[0, 0, 0] - (NS - 1) * v * v * gamma) < 1e-15
+    # Eq. tilde_Phi_GW: only W = 0 carries P0, so Phi~ = (ln(1 + a) - a) / (2 beta)
+    assert abs(gw.phi_gw(d["P0w"], g, 1) - (np.log1p(a) - a) / (2 * beta)) < 1e-13
+
+
+def test_phi_gw_second_order_limit():
+    """Eq. tilde_Phi_GW for small P0 is -(1/4) Tr{P0^2} (the paper's expansion),
+    with Tr{P0^2} = (1/Nk) sum_q int_0^beta tr[P0^q(tau) P0^q(beta - tau)] d tau
+    taken by Chebyshev integration of the interpolant on the tau nodes: an
+    independent route to the Matsubara-weight quadrature of phi_gw."""
+    wl, g, H0, S, V, G = _setup(mesh=(2, 1, 1), nao=3, naux=4, ntau=24, beta=5.0)
+    # interpolatory integration weights: int_0^beta T_l(2 tau / beta - 1) = beta/(1 - l^2), l even
+    Cm = np.cos(np.outer(np.arccos(g.x), np.arange(wl.ntau)))
+    il = np.array([wl.beta / (1.0 - l * l) if l % 2 == 0 else 0.0 for l in range(wl.ntau)])
+    wint = il @ np.linalg.inv(Cm)
+    ratios = []
+    for s in (3e-2, 1e-2, 3e-3):
+        _, _, d = gw.sigma_evaluation(V * s / 0.1, G, g, wl.mesh, NS)
+        P0 = d["P0"]
+        tr2 = sum(wint @ np.array([np.trace(P0[q, i] @ P0[q, wl.ntau - 1 - i]).real
+                                   for i in range(wl.ntau)]) for q in range(wl.nk)) / wl.nk
+        ratios.append(gw.phi_gw(d["P0w"], g, wl.nk) / (-0.25 * tr2))
+    print("Phi~ / (-Tr P0^2 / 4):", ratios)
+    # the ratio tends to 1 with corrections of order P0, i.e. as s^2 (about a
+    # tenth per step here), above a floor of about 4e-5 from the two
+    # quadratures on 24 nodes
+    dev_ = [abs(r - 1.0) for r in ratios]
+    assert dev_[2] < 5e-4
+    assert dev_[0] > 6 * dev_[1] and dev_[1] > 6 * dev_[2]
 
 
 # ---------------------------------------------------------------- invariants -
