@@ -297,6 +297,41 @@ def test_phi_gw_second_order_limit():
     assert dev_[0] > 6 * dev_[1] and dev_[1] > 6 * dev_[2]
 
 
+@pytest.mark.parametrize("ntau", [16, 24])
+def test_phi_derivability(ntau):
+    """Sigma~ = delta Phi~ / delta G (Sec. III.C): along a smooth direction dG,
+    d/dh Phi~[G + h dG] = Tr{Sigma~ dG} = -(ns/Nk) sum_k int_0^beta
+    tr[Sigma~^k(tau) dG^k(beta - tau)] d tau (the fermionic Matsubara sum of
+    a product in tau, with Sigma~ per spin and the trace over spin-orbitals).
+    Central differences of phi_gw against the oracle's own self-energy,
+    integrated by Chebyshev weights on the nodes: this ties the signs and
+    factors of the polarization, the screened-interaction solve and the
+    self-energy contraction to the Luttinger-Ward functional."""
+    beta = 5.0
+    wl = inp.small_workload(mesh=(2, 1, 1), nao=3, naux=4, ntau=ntau, beta=beta, seed=3)
+    g = og.Grids(beta, ntau)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), 3.0 * inp.make_V(wl)
+    G = gw.g0_tau(H0, S, 0.1, beta, g.tau)
+    rng = np.random.default_rng(4)
+    Hp = inp.random_hermitian_tau(rng, 1, wl.nk, wl.nao, 0.3)[0]
+    dG = gw.g0_tau(H0 + Hp, S, 0.1, beta, g.tau) - G
+
+    def phi(Gx):
+        return gw.phi_gw(gw.sigma_evaluation(V, Gx, g, wl.mesh, NS)[2]["P0w"], g, wl.nk)
+
+    h = 1e-5
+    fd = (phi(G + h * dG) - phi(G - h * dG)) / (2 * h)
+    _, stau, _ = gw.sigma_evaluation(V, G, g, wl.mesh, NS)
+    Cm = np.cos(np.outer(np.arccos(g.x), np.arange(ntau)))
+    il = np.array([beta / (1.0 - l * l) if l % 2 == 0 else 0.0 for l in range(ntau)])
+    wint = il @ np.linalg.inv(Cm)
+    pred = -NS / wl.nk * sum(wint[i] * np.trace(stau[i, k] @ dG[ntau - 1 - i, k]).real
+                             for i in range(ntau) for k in range(wl.nk))
+    print("d Phi~ / dh", fd, "Tr{Sigma~ dG}", pred)
+    assert abs(pred) > 1e-3
+    assert abs(fd - pred) < 1e-7 * abs(pred)
+
+
 # ---------------------------------------------------------------- invariants -
 def test_invariants():
     wl, g, H0, S, V, G = _setup(mesh=(3, 1, 1), nao=3, naux=4, ntau=12, beta=10.0)
