@@ -5,7 +5,7 @@ by the GW equations of the paper.  It is imported only by tests, by the
 smoke check and by the CPU-baseline timing; the product path never runs it.
 
 The paper expands dynamical quantities in the IR basis with sparse sampling
-(Sec. IV.C).  That package is not available here; this build samples tau at
+(Sec. IV.C).  That package is not used; tau is sampled at
 Chebyshev roots instead and picks a sparse Matsubara set greedily.  Readings
 taken (each also listed in the design notes):
 
