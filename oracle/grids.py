@@ -6,7 +6,7 @@ smoke check and by the CPU-baseline timing; the product path never runs it.
 
 The paper expands dynamical quantities in the IR basis with sparse sampling
 (Sec. IV.C).  That package is not used; tau is sampled at
-Chebyshev roots instead and picks a sparse Matsubara set greedily.  Readings
+Chebyshev roots instead, and a sparse Matsubara set is picked greedily.  Readings
 taken (each also listed in the design notes):
 
 * tau nodes: roots of T_n on [-1,1] mapped to [0, beta], mirrored so that
