@@ -213,6 +213,56 @@ def compare_solvers(path, wl, tol):
             "gflop_per_sigma_evaluation": flops / 1e9}
 
 
+def compare_precisions(path64, V, H0, S, wl, tol):
+    """Whole self-consistent solves to max |Sigma[G(x)] - x| < tol from G0:
+    the plain damped fp64 loop, DIIS in fp64 and DIIS in the mixed path
+    (complex64 V, fp32 MFMA contractions); seconds, evaluations, and how far
+    the mixed fixed point lies from the fp64 one (equal-accuracy check)."""
+    import torch
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.diis import DIIS
+    from paper_2206_07660_amd.scgw import GWPath
+    out = {"metric": "scGW solve to equal residual: plain fp64 loop vs DIIS fp64 vs DIIS mixed",
+           "workload": wl.name, "tol_max_abs_residual_Ha": tol}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = path64.start(0.0)
+    n_fp = 0
+    while n_fp < 80:
+        path64.step(st)
+        n_fp += 1
+        log(f"[precisions] fp64 damped {n_fp}: dSigma {st.dsig:.3e}")
+        if st.dsig < tol:
+            break
+    torch.cuda.synchronize()
+    out["fp64_damped"] = {"iterations": n_fp, "sigma_evaluations": n_fp,
+                          "seconds": time.perf_counter() - t0, "final_dsigma": st.dsig}
+    fp_inf, fp_tau = st.sig_inf.clone(), st.sig_tau.clone()
+    sols = {}
+    ctx32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision="fp32")
+    p32 = GWPath(ctx32, V.to(torch.complex64), H0, S, wl.n_target)
+    for name, p in (("fp64_diis", path64), ("mixed_diis", p32)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s0 = p.start(0.0)
+        dz = DIIS(p, depth=6)
+        x, F = dz.solve(s0.sig_inf, s0.sig_tau, s0.mu, tol=tol, max_iter=60,
+                        log=lambda m, n=name: log(f"[precisions] {n} {m}"))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        sols[name] = (dz.inf(x).clone(), dz.tau(x).clone())
+        out[name] = {"iterations": dz.stats.iterations, "sigma_evaluations": dz.stats.evaluations,
+                     "seconds": sec, "residuals": dz.stats.residuals, "mu": dz.mu}
+    d = lambda a, b: max((a[0] - b[0]).abs().max().item(), (a[1] - b[1]).abs().max().item())
+    out["max_abs_sigma_fp64_diis_vs_damped_Ha"] = d(sols["fp64_diis"], (fp_inf, fp_tau))
+    out["max_abs_sigma_mixed_vs_fp64_Ha"] = d(sols["mixed_diis"], sols["fp64_diis"])
+    out["speedup_fp64_diis_over_damped"] = out["fp64_damped"]["seconds"] / out["fp64_diis"]["seconds"]
+    out["speedup_mixed_diis_over_damped"] = out["fp64_damped"]["seconds"] / out["mixed_diis"]["seconds"]
+    out["speedup_mixed_over_fp64_diis"] = out["fp64_diis"]["seconds"] / out["mixed_diis"]["seconds"]
+    ctx32.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +277,10 @@ def main():
                     help="instead of the step benchmark: damped fixed point vs DIIS vs Newton-Krylov "
                          "to the same residual (default workload ad-3x3x3)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--compare-precisions", action="store_true",
+                    help="instead of the step benchmark: plain fp64 damped loop vs DIIS in fp64 "
+                         "and in mixed precision to --tol-mixed (default workload si-4x4x4)")
+    ap.add_argument("--tol-mixed", type=float, default=1e-6)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -266,6 +320,10 @@ def main():
     path = GWPath(ctx, V, H0, S, wl.n_target, alpha=0.5)
     if args.compare_solvers:
         print(json.dumps(compare_solvers(path, wl, args.tol)), flush=True)
+        ctx.close()
+        return
+    if args.compare_precisions:
+        print(json.dumps(compare_precisions(path, V, H0, S, wl, args.tol_mixed)), flush=True)
         ctx.close()
         return
     st = path.start(0.0)
