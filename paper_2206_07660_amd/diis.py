@@ -44,6 +44,12 @@ class DIISCore:
     def __len__(self):
         return len(self.xs)
 
+    def reset(self):
+        """Forget the history (the buffers are released)."""
+        self.xs, self.fs = [], []
+        self.B = np.zeros((0, 0))
+        self.last_coefficients = np.zeros(0)
+
     def push(self, x, f):
         """Append copies of x and F(x); drops the oldest pair beyond depth."""
         if len(self.xs) == self.depth:
@@ -159,6 +165,7 @@ class DIIS:
         iteration is started (the last residual is returned)."""
         gw, c = self.gw, self.ctx
         self.mu = mu0
+        self.core.reset()                     # a new solve starts without history
         x, F = self.vec(), self.vec()
         gw.gw_axpby(c, 1.0, sig_inf, 0.0, self.inf(x))
         gw.gw_axpby(c, 1.0, sig_tau, 0.0, self.tau(x))

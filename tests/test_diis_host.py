@@ -99,3 +99,17 @@ def test_linear_fixed_point_converges_in_about_n_iterations():
     for _ in range(n + 2):
         y = A @ y + b
     assert np.abs(y - x_star).max() > 1e-3
+
+
+def test_reset_forgets_the_history():
+    rng = np.random.default_rng(9)
+    core = np_core(depth=4)
+    for _ in range(3):
+        core.push(rng.normal(size=N_DIM) + 0j, rng.normal(size=N_DIM) + 0j)
+    core.reset()
+    assert len(core) == 0 and core.B.shape == (0, 0)
+    x, f = rng.normal(size=N_DIM) + 0j, rng.normal(size=N_DIM) + 0j
+    core.push(x, f)
+    out = np.empty(N_DIM, complex)
+    c = core.extrapolate(out)
+    assert np.allclose(c, [1.0]) and np.allclose(out, x + f)
