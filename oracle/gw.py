@@ -87,39 +87,50 @@ def electron_count(gamma, S, ns):
 # ---------------------------------------------------- HF (Eqs. HF_J, HF_K) ---
 def hartree_fock(V, gamma, mesh, ns):
     """Sigma_inf^k = J^k + K^k, with V^{k,k+q}(Q) = V[q][k][Q] and
-    V^{k+q,k}(Q) = V[q][k][Q]^dagger."""
+    V^{k+q,k}(Q) = V[q][k][Q]^dagger:
+    J^k = sum_Q v_Q V^{kk}(Q), v_Q = (ns/Nk) sum_k' tr[gamma^k' V^{k'k'}(Q)];
+    K^k = -(1/Nk) sum_q sum_Q V^{k,k+q}(Q) gamma^{k+q} V^{k+q,k}(Q)."""
     plus, _ = mesh_tables(mesh)
-    nk = gamma.shape[0]
-    vQ = np.zeros(V.shape[2], np.complex128)
+    nk, n, _ = gamma.shape
+    naux = V.shape[2]
+    vQ = np.zeros(naux, np.complex128)
     for kp in range(nk):
         vQ += ns / nk * np.einsum("ab,Qba->Q", gamma[kp], V[0, kp])
     J = np.einsum("Q,kQij->kij", vQ, V[0])
     K = np.zeros_like(gamma)
     for k in range(nk):
         for q in range(nk):
-            A = V[q, k]
-            K[k] -= 1.0 / nk * np.einsum("Qia,ab,Qjb->ij", A, gamma[plus[q, k]], A.conj())
+            A = V[q, k]                                             # (Q, i, a)
+            T = (A.reshape(naux * n, n) @ gamma[plus[q, k]]).reshape(naux, n, n)   # (Q, i, b)
+            Tf = np.swapaxes(T, 0, 1).reshape(n, naux * n)          # (i, (Q b))
+            K[k] -= 1.0 / nk * (Tf @ np.swapaxes(np.conj(A), 1, 2).reshape(naux * n, n))
     return J + K
 
 
 # ------------------------------------------ polarization (Eq. tilde_P0_tau) --
 def polarization(V, G_tau, mesh, ns, qs=None, taus=None):
     """P0^q_{QQ'}(tau_i) = -(ns/Nk) sum_k sum_{abcd} V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_i)
-    V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau_i)  (reading R1)."""
+    V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau_i)  (reading R1).
+
+    Loops over q and tau.  For each k, X(Q) = V^{k,k+q}(Q) G^{k+q}(tau) and
+    Z(Q') = V^{k+q,k}(Q') G^k(beta - tau); the sum over (k, d, b) of
+    X_{db}(Q) Z_{bd}(Q') is one matmul of X flattened over (k, d, b) with Z
+    transposed to (k, d, b)."""
     plus, _ = mesh_tables(mesh)
-    ntau, nk = G_tau.shape[:2]
+    ntau, nk, n, _ = G_tau.shape
     naux = V.shape[2]
-    qs = range(nk) if qs is None else qs
-    taus = range(ntau) if taus is None else taus
+    qs = list(range(nk)) if qs is None else list(qs)
+    taus = list(range(ntau)) if taus is None else list(taus)
     out = np.zeros((len(qs), len(taus), naux, naux), np.complex128)
     for iq, q in enumerate(qs):
-        for k in range(nk):
-            A = V[q, k]                                   # (Q, d, a)
-            Ah = np.conj(np.swapaxes(A, 1, 2))           # V^{k+q,k}(Q') as (Q', b, c)
-            for it, t in enumerate(taus):
-                X = A @ G_tau[t, plus[q, k]]              # (Q, d, b)
-                Z = Ah @ G_tau[ntau - 1 - t, k]           # (Q', b, d)
-                out[iq, it] -= ns / nk * np.einsum("Qdb,Pbd->QP", X, Z, optimize=True)
+        A = V[q].reshape(nk, naux * n, n)                               # (k, (Q d), a)
+        Ah = np.conj(np.swapaxes(V[q], 2, 3)).reshape(nk, naux * n, n)  # V^{k+q,k}(Q') as (k, (Q' b), c)
+        for it, t in enumerate(taus):
+            X = np.matmul(A, G_tau[t, plus[q]]).reshape(nk, naux, n, n)            # (k, Q, d, b)
+            Z = np.matmul(Ah, G_tau[ntau - 1 - t]).reshape(nk, naux, n, n)         # (k, Q', b, d)
+            Xf = np.swapaxes(X, 0, 1).reshape(naux, nk * n * n)                    # (Q, (k d b))
+            Zf = np.swapaxes(np.swapaxes(Z, 2, 3), 0, 1).reshape(naux, nk * n * n)  # (Q', (k d b))
+            out[iq, it] = -ns / nk * (Xf @ Zf.T)
     return out
 
 
@@ -152,19 +163,24 @@ def self_energy(V, G_tau, Pt_tau, mesh, qs=None, out=None):
     V^{k,k-q}_{ia}(Q) P~^q_{QQ'}(tau) V^{k-q,k}_{bj}(Q').
 
     V^{k-q,k}(Q) = V[q][k-q][Q]; V^{k,k-q}(Q) is its conjugate transpose.
-    Pt_tau[iq] belongs to q = qs[iq]."""
-    _, minus = mesh_tables(mesh)
+    Pt_tau[iq] belongs to q = qs[iq].  Loops over q and tau; with p = k - q
+    running over the slab: B_{bj}(Q) = sum_Q' P~_{QQ'} V^{p,p+q}_{bj}(Q') for
+    all p at once (one matmul), L_{ib}(Q) = sum_a V^{p+q,p}_{ia}(Q)
+    G^p_{ab}(tau), and Sigma~^{p+q} -= (1/Nk) sum_{Q,b} L_{ib}(Q) B_{bj}(Q)."""
+    plus, _ = mesh_tables(mesh)
     ntau, nk, n, _ = G_tau.shape
+    naux = V.shape[2]
     qs = range(nk) if qs is None else qs
     out = np.zeros_like(G_tau) if out is None else out
     for iq, q in enumerate(qs):
-        for k in range(nk):
-            kk = minus[q, k]
-            A = V[q, kk]                                   # (Q, b, j) = V^{k-q,k}
-            for t in range(ntau):
-                B = np.tensordot(Pt_tau[iq, t], A, axes=(1, 0))      # (Q, b, j)
-                out[t, k] -= 1.0 / nk * np.einsum("Qai,ab,Qbj->ij", A.conj(), G_tau[t, kk], B,
-                                                   optimize=True)
+        Vs = np.swapaxes(V[q], 0, 1).reshape(naux, nk * n * n)          # (Q', (p b j))
+        Ac = np.conj(np.swapaxes(V[q], 2, 3)).reshape(nk, naux * n, n)  # V^{p+q,p}(Q) as (p, (Q i), a)
+        for t in range(ntau):
+            B = (Pt_tau[iq, t] @ Vs).reshape(naux, nk, n, n)                        # (Q, p, b, j)
+            L = np.matmul(Ac, G_tau[t]).reshape(nk, naux, n, n)                     # (p, Q, i, b)
+            Lf = np.swapaxes(L, 1, 2).reshape(nk, n, naux * n)                      # (p, i, (Q b))
+            Bf = np.swapaxes(B, 0, 1).reshape(nk, naux * n, n)                      # (p, (Q b), j)
+            out[t, plus[q]] -= 1.0 / nk * np.matmul(Lf, Bf)
     return out
 
 
