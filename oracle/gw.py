@@ -188,7 +188,7 @@ def self_energy(V, G_tau, Pt_tau, mesh, qs=None, out=None):
 def dyson(H0, S, Sig_inf, Sig_iw, mu, wF):
     """G^k(i w_n) = [(i w_n + mu) S^k - H0^k - Sigma_inf^k - Sigma~^k(i w_n)]^{-1}."""
     nw, nk, n, _ = Sig_iw.shape
-    G = np.empty_like(Sig_iw)
+    G = np.empty(Sig_iw.shape, np.complex128)
     for iw in range(nw):
         for k in range(nk):
             M = (1j * wF[iw] + mu) * S[k] - H0[k] - Sig_inf[k] - Sig_iw[iw, k]
