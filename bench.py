@@ -368,7 +368,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": None,                      # one GPU: no scaling regime
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",

@@ -63,7 +63,8 @@ typedef enum {
   GW_ERR_SINGULAR = 3,   /* a zero pivot in a Dyson solve                    */
   GW_ERR_NOCONV = 4,     /* mu search did not bracket or converge            */
   GW_ERR_WORKSPACE = 5,  /* workspace missing or too small                   */
-  GW_ERR_STATE = 6       /* call made before gw_build_grids                  */
+  GW_ERR_STATE = 6,      /* call made before gw_build_grids / gw_set_grids   */
+  GW_ERR_NONFINITE = 7   /* a NaN or Inf met where a finite value is needed  */
 } gw_status;
 
 enum { GW_FERMION = 0, GW_BOSON = 1 };
@@ -86,8 +87,10 @@ typedef struct {
   int nao;         /* orbitals per cell, 1..60                                */
   int naux;        /* auxiliary functions Q, >= 1                             */
   int ntau;        /* imaginary-time nodes, even, 2..512                      */
-  int nw_f;        /* fermionic sparse frequencies; must equal ntau           */
-  int nw_b;        /* bosonic sparse frequencies; must equal ntau + 1         */
+  int nw_f;        /* fermionic sparse frequencies, ntau..4 ntau (gw_build_grids:
+                      exactly ntau)                                           */
+  int nw_b;        /* bosonic sparse frequencies, ntau..4 ntau + 1 (gw_build_grids:
+                      exactly ntau + 1)                                       */
   int ns;          /* spin factor, 1 or 2                                     */
   int precision;   /* GW_PREC_*                                               */
   double beta;     /* inverse temperature (1/Ha), > 0                         */
@@ -120,6 +123,27 @@ gw_status gw_destroy(gw_ctx* ctx);
  * Host-only arithmetic; synchronises once for the uploads.                  */
 gw_status gw_build_grids(gw_ctx* ctx, const long long* nF, const long long* nB);
 
+/* Install caller-built grid tables in place of gw_build_grids (Sec. IV.C:
+ * any sparse representation on the imaginary axes whose tables have these
+ * meanings, e.g. an intermediate-representation basis with its sampling
+ * points).  All arrays are HOST arrays, row-major, copied by the call:
+ *   tau[ntau]        nodes in (0, beta), strictly increasing and mirrored,
+ *                    |tau_{ntau-1-i} - (beta - tau_i)| <= 1e-12 beta (the
+ *                    polarization reads G(beta - tau_i) as node ntau-1-i)
+ *   nF[nw_f], nB[nw_b]  Matsubara indices (omega_n = (2n+1) pi / beta,
+ *                    Omega_m = 2 m pi / beta), strictly increasing
+ *   TF[nw_f*ntau], TB[nw_b*ntau]     tau -> i w transforms (Eqs. tau_to_iw,
+ *                    P0t_to_P0w): X(i w_n) = sum_i T[n][i] X(tau_i)
+ *   TFp[ntau*nw_f], TBp[ntau*nw_b]   i w -> tau fits (Eqs. iw_to_tau,
+ *                    Piw_to_Pt): X(tau_i) = sum_n Tp[i][n] X(i w_n)
+ *   w[ntau]          density row: gamma = -G(beta^-) = -sum_i w_i G(tau_i)
+ * Non-finite entries or violated orderings are GW_ERR_ARG (nothing is
+ * changed).  The electron-count row r = w TFp and the frequency values are
+ * derived here.  Synchronises once for the uploads.                         */
+gw_status gw_set_grids(gw_ctx* ctx, const double* tau, const long long* nF, const long long* nB,
+                       const gw_z* TF, const gw_z* TFp, const gw_z* TB, const gw_z* TBp,
+                       const double* w);
+
 /* Copy the host tables out (each pointer is a HOST array and may be NULL):
  * tau[ntau], nF[nw_f], nB[nw_b], TF[nw_f*ntau], TFp[ntau*nw_f],
  * TB[nw_b*ntau], TBp[ntau*nw_b] (row-major), w[ntau].                       */
@@ -137,11 +161,13 @@ gw_status gw_grids_host(double beta, int ntau, const long long* nF, const long l
 /* Workspace.  gw_workspace_bytes returns the bytes a call needs: op is one of
  * GW_OP_*; for the chains, tau_chunk (1..ntau) is how many tau nodes are
  * processed per pass (memory grows linearly with it); for GW_OP_SCREENED_W,
- * tau_chunk is read as nq.  gw_set_workspace hands over a device buffer
+ * tau_chunk is read as nq; GW_OP_SIGMA (gw_sigma, gw_sigma_jvp,
+ * gw_sigma_vjp) is the largest of the chain, Hartree-Fock and one-q
+ * screened-interaction needs plus six per-q polarization buffers.  gw_set_workspace hands over a device buffer
  * (caller-owned, >= 256-byte aligned) and the tau chunk to use; calls that
  * need more than that buffer return GW_ERR_WORKSPACE.                       */
 enum { GW_OP_POLARIZATION = 0, GW_OP_SELF_ENERGY = 1, GW_OP_SCREENED_W = 2, GW_OP_HF = 3,
-       GW_OP_DYSON_JVP = 4 };
+       GW_OP_DYSON_JVP = 4, GW_OP_SIGMA = 5 };
 size_t gw_workspace_bytes(const gw_ctx* ctx, int op, int tau_chunk);
 gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
 
@@ -231,10 +257,13 @@ gw_status gw_dyson_G(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig
  * On return *mu_inout is the midpoint, G_iw (may be NULL) holds G at that mu,
  * G_tau (may be NULL) its transform to the tau nodes, *n_out (may be NULL)
  * the electron count there.  n_target outside (0, ns*nao) is GW_ERR_ARG; a
- * bracket that cannot be found is GW_ERR_NOCONV.  With a window set by
- * gw_set_mu_window the result is instead *mu_inout itself if its count is
- * within the window of n_target, else the midpoint of the two roots of
- * N_e(mu) = n_target -/+ window (each found the same way).  Synchronises.   */
+ * bracket that cannot be found, or a bisection that cannot narrow the
+ * bracket to tol within 400 halvings (tol below the spacing of doubles near
+ * mu), is GW_ERR_NOCONV; a non-finite electron count is GW_ERR_NONFINITE.
+ * With a window set by gw_set_mu_window the result is instead *mu_inout
+ * itself if its count is within the window of n_target, else the midpoint of
+ * the two roots of N_e(mu) = n_target -/+ window (each found the same way).
+ * Synchronises.                                                             */
 gw_status gw_find_mu(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig_inf,
                      const gw_z* Sig_iw, double n_target, double tol, double* mu_inout,
                      gw_z* G_iw, gw_z* G_tau, double* n_out);
@@ -268,11 +297,32 @@ gw_status gw_set_mu_window(gw_ctx* ctx, double ne_tol);
 gw_status gw_finite_size(gw_ctx* ctx, const gw_z* S, double chi, const gw_z* gamma, gw_z* Sig_inf,
                          const gw_z* G_tau, const double* head, gw_z* Sig_tau);
 
+/* One whole Sigma[G] + Pi evaluation (Sec. III, Algorithm 1): gamma and
+ * Sigma_inf = J + K (as gw_hf), then for every q P0^q(tau) (Eq.
+ * tilde_P0_tau; Hermitian mode as set by gw_set_hermitian), P0^q(i Omega),
+ * P~^q(i Omega) = (I - P0)^{-1} P0 (Eq. tilde_P_omega), P~^q(tau), and
+ * Sig_tau = Sigma~(tau) (Eq. tilde_sigma2, overwritten).
+ * Polarization storage, either all three or none:
+ *   P_tau [Nk][ntau][naux][naux]: receives P~(tau) (P0(tau) on the way);
+ *   P0_iw, Pt_iw [Nk][nw_b][naux][naux]: P0(i Omega) and P~(i Omega).
+ *   These are what gw_sigma_jvp / gw_sigma_vjp take.  With all three NULL the
+ *   evaluation runs q by q in per-q buffers of the workspace (GW_OP_SIGMA)
+ *   and keeps nothing.  The screened-interaction solves of the stored form
+ *   run in q-batches as large as the workspace holds.
+ * gamma (may be NULL) receives gamma = -G(beta^-).  phi (host, may be NULL)
+ * receives Phi~ (Eq. tilde_Phi_GW, as gw_screened_W_phi over all q) and makes
+ * the call synchronise.  Errors as the calls it is made of.                 */
+gw_status gw_sigma(gw_ctx* ctx, const void* V, const gw_z* G_tau, gw_z* gamma, gw_z* Sig_inf,
+                   gw_z* Sig_tau, gw_z* P_tau, gw_z* P0_iw, gw_z* Pt_iw, double* phi);
+
 /* Damped update and convergence measure of the scGW loop (Sec. IV.A):
  * Y <- (1 - alpha) Y + alpha X_new over n complex elements.  X_new may be
  * NULL, in which case Y <- (1 - alpha) Y, and alpha = 1 writes zeros without
  * reading Y.  maxdiff (host, may be NULL) receives max_i |X_new[i] - Y_old[i]|
- * (max |Y_old[i]| when X_new is NULL) and makes the call synchronise.       */
+ * (max |Y_old[i]| when X_new is NULL) and makes the call synchronise; if that
+ * maximum is not finite (a NaN or Inf element, or Inf - Inf) the update is
+ * still made, *maxdiff holds the non-finite value and the call returns
+ * GW_ERR_NONFINITE, so that no convergence test passes on such a state.    */
 gw_status gw_mix(gw_ctx* ctx, long long n, double alpha, const gw_z* X_new, gw_z* Y,
                  double* maxdiff);
 
@@ -334,6 +384,27 @@ gw_status gw_hf_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* Sinf_bar, gw_z* G_ba
  * GW_OP_DYSON_JVP workspace.                                                */
 gw_status gw_dyson_jvp(gw_ctx* ctx, const gw_z* S, const gw_z* G_iw, const gw_z* dSinf,
                        const gw_z* dSig_iw, int fixed_mu, gw_z* dG_iw, double* dmu);
+
+/* Whole-chain derivatives of G -> (Sigma_inf[G], Sigma~[G]), the composition
+ * of the calls above (derivative of the chain of Eqs. HF_J, HF_K,
+ * tilde_P0_tau, P0t_to_P0w, tilde_P_omega, Piw_to_Pt, tilde_sigma2):
+ *   JVP  dSig_inf = HF[gamma(dG)],  dP0 = P0[dG, G] + P0[G, dG],
+ *        dP~(i Omega) = (I + P~) dP0(i Omega) (I + P~),
+ *        dSig_tau = Sigma~[dP~, G] + Sigma~[P~, dG];
+ *   VJP  G_bar = the conjugate-transposed steps applied to (Sinf_bar,
+ *        Stau_bar) in reverse order (torch's convention for complex inputs).
+ * Pt_tau [Nk][ntau][naux][naux] and Pt_iw [Nk][nw_b][naux][naux] are P~ of G
+ * for all q as gw_sigma leaves them; with both NULL, P~^q is rebuilt q by q
+ * inside the call from G (one polarization, transform and solve per q, with
+ * the Hermitian mode of gw_set_hermitian), so nothing of size Nk naux^2 is
+ * held.  The JVP uses GW_HERM_TWO_SLOT when set (dG Hermitian like G).
+ * Outputs are overwritten: dSig_inf [k][i][j], dSig_tau and G_bar
+ * [tau][k][i][j].  Workspace GW_OP_SIGMA.  The JVP runs in either precision,
+ * the VJP needs a GW_PREC_FP64 context.                                     */
+gw_status gw_sigma_jvp(gw_ctx* ctx, const void* V, const gw_z* G_tau, const gw_z* Pt_tau,
+                       const gw_z* Pt_iw, const gw_z* dG_tau, gw_z* dSig_inf, gw_z* dSig_tau);
+gw_status gw_sigma_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* Pt_tau,
+                       const gw_z* Pt_iw, const gw_z* Sinf_bar, const gw_z* Stau_bar, gw_z* G_bar);
 
 /* Vector operations of the Newton-Krylov solver: Y = a X + b Y for complex
  * a, b over n elements (X may be NULL; b = 0 does not read Y), and

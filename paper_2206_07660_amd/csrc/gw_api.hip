@@ -44,6 +44,7 @@ struct gw_ctx {
   int* dflag = nullptr;
   double* dpart = nullptr;   // nw_f * nk partials, then the reduced scalar at [nw_f*nk]
   double* dred = nullptr;    // 2 * 1024 partials + 2 results for gw_dot
+  double* dphi = nullptr;    // Nk * nw_b per-matrix terms of Phi~, then their sum
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int tc = 0;
@@ -78,8 +79,11 @@ gw_status check_dims(const gw_dims* d, std::string& why) {
   if (d->nao < 1 || d->nao > 60) { why = "nao must be in 1..60"; return GW_ERR_ARG; }
   if (d->naux < 1 || d->naux > 8192) { why = "naux must be in 1..8192"; return GW_ERR_ARG; }
   if (d->ntau < 2 || d->ntau > 512 || d->ntau % 2) { why = "ntau must be even, 2..512"; return GW_ERR_ARG; }
-  if (d->nw_f != d->ntau) { why = "nw_f must equal ntau"; return GW_ERR_ARG; }
-  if (d->nw_b != d->ntau + 1) { why = "nw_b must equal ntau + 1"; return GW_ERR_ARG; }
+  if (d->nw_f < d->ntau || d->nw_f > 4 * d->ntau) { why = "nw_f must lie in ntau..4 ntau"; return GW_ERR_ARG; }
+  if (d->nw_b < d->ntau || d->nw_b > 4 * d->ntau + 1) {
+    why = "nw_b must lie in ntau..4 ntau + 1";
+    return GW_ERR_ARG;
+  }
   if (d->ns != 1 && d->ns != 2) { why = "ns must be 1 or 2"; return GW_ERR_ARG; }
   if (!(d->beta > 0.0) || !std::isfinite(d->beta)) { why = "beta must be positive"; return GW_ERR_ARG; }
   if (d->precision != GW_PREC_FP64 && d->precision != GW_PREC_FP32) {
@@ -235,6 +239,7 @@ gw_status count_at(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf, c
   HIPCHK(c, sum_launch(c->dpart, np, -(double)c->d.ns / c->nk, c->dpart + np, c->st));
   HIPCHK(c, hipMemcpyAsync(ne, c->dpart + np, sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  if (!std::isfinite(*ne)) return fail(c, GW_ERR_NONFINITE, "electron count is not finite");
   return GW_OK;
 }
 
@@ -251,6 +256,7 @@ const char* gw_status_string(gw_status s) {
     case GW_ERR_NOCONV: return "no convergence";
     case GW_ERR_WORKSPACE: return "workspace missing or too small";
     case GW_ERR_STATE: return "grids not built";
+    case GW_ERR_NONFINITE: return "non-finite value";
   }
   return "unknown status";
 }
@@ -291,7 +297,8 @@ gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
       hipMalloc((void**)&c->dflag, sizeof(int)) != hipSuccess ||
       hipMemset(c->dflag, 0, sizeof(int)) != hipSuccess ||
       hipMalloc((void**)&c->dpart, ((size_t)d->nw_f * c->nk + 8) * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&c->dred, (2 * 1024 + 8) * sizeof(double)) != hipSuccess) {
+      hipMalloc((void**)&c->dred, (2 * 1024 + 8) * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&c->dphi, ((size_t)d->nw_b * c->nk + 8) * sizeof(double)) != hipSuccess) {
     gw_destroy(c);
     return GW_ERR_DEVICE;
   }
@@ -307,7 +314,7 @@ gw_status gw_destroy(gw_ctx* c) {
       (void)hipEventDestroy(p.second);
     }
   void* ptrs[] = {c->dTF, c->dTFp, c->dTB, c->dTBp, c->dw, c->drrow, c->dwF,
-                  c->dplus, c->dminus, c->dflag, c->dpart, c->dred};
+                  c->dplus, c->dminus, c->dflag, c->dpart, c->dred, c->dphi};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -320,6 +327,19 @@ struct HostGrids {
   std::vector<gwgrid::cd> TF, TFp, TB, TBp, rrow;
   std::vector<double> wf;
 };
+
+// Derived tables: fermionic frequencies and the electron-count row r = w TFp.
+static void finish_grids(double beta, HostGrids& g) {
+  const int nt = (int)g.tau.size(), nwf = (int)g.nF.size();
+  g.wf.assign(nwf, 0.0);
+  for (int n = 0; n < nwf; ++n) g.wf[n] = gwgrid::matsubara(g.nF[n], beta, 0);
+  g.rrow.assign(nwf, 0.0);
+  for (int n = 0; n < nwf; ++n) {
+    gwgrid::cd s = 0.0;
+    for (int i = 0; i < nt; ++i) s += g.w[i] * g.TFp[(size_t)i * nwf + n];
+    g.rrow[n] = s;
+  }
+}
 
 static gw_status make_grids(double beta, int nt, const long long* nF, const long long* nB,
                             HostGrids& g, std::string& why) {
@@ -338,15 +358,14 @@ static gw_status make_grids(double beta, int nt, const long long* nF, const long
       if (g.nF[i] <= g.nF[i - 1]) { why = "nF must be strictly increasing"; return GW_ERR_ARG; }
     for (size_t i = 1; i < g.nB.size(); ++i)
       if (g.nB[i] <= g.nB[i - 1]) { why = "nB must be strictly increasing"; return GW_ERR_ARG; }
-    g.wf.assign(nwf, 0.0);
-    std::vector<double> wb(nwb);
-    for (int n = 0; n < nwf; ++n) g.wf[n] = gwgrid::matsubara(g.nF[n], beta, 0);
+    std::vector<double> wf(nwf), wb(nwb);
+    for (int n = 0; n < nwf; ++n) wf[n] = gwgrid::matsubara(g.nF[n], beta, 0);
     for (int n = 0; n < nwb; ++n) wb[n] = gwgrid::matsubara(g.nB[n], beta, 1);
     g.TF.assign((size_t)nwf * nt, 0.0);
     g.TB.assign((size_t)nwb * nt, 0.0);
     g.TFp.assign((size_t)nt * nwf, 0.0);
     g.TBp.assign((size_t)nt * nwb, 0.0);
-    gwgrid::transform(beta, nt, g.x.data(), g.wf.data(), nwf, g.TF.data());
+    gwgrid::transform(beta, nt, g.x.data(), wf.data(), nwf, g.TF.data());
     gwgrid::transform(beta, nt, g.x.data(), wb.data(), nwb, g.TB.data());
     if (gwgrid::pinv_qr(g.TF.data(), nwf, nt, g.TFp.data()) ||
         gwgrid::pinv_qr(g.TB.data(), nwb, nt, g.TBp.data())) {
@@ -355,12 +374,7 @@ static gw_status make_grids(double beta, int nt, const long long* nF, const long
     }
     g.w.assign(nt, 0.0);
     gwgrid::beta_row(nt, g.x.data(), g.w.data());
-    g.rrow.assign(nwf, 0.0);
-    for (int n = 0; n < nwf; ++n) {
-      gwgrid::cd s = 0.0;
-      for (int i = 0; i < nt; ++i) s += g.w[i] * g.TFp[(size_t)i * nwf + n];
-      g.rrow[n] = s;
-    }
+    finish_grids(beta, g);
   } catch (const std::exception& e) {
     why = e.what();
     return GW_ERR_ARG;
@@ -386,12 +400,8 @@ gw_status gw_grids_host(double beta, int ntau, const long long* nF, const long l
   return GW_OK;
 }
 
-gw_status gw_build_grids(gw_ctx* c, const long long* nF, const long long* nB) {
-  if (!c) return GW_ERR_ARG;
-  HostGrids g;
-  std::string why;
-  gw_status s = make_grids(c->d.beta, c->d.ntau, nF, nB, g, why);
-  if (s != GW_OK) return fail(c, s, why);
+// Keep the host tables in the context and upload the device copies.
+static gw_status install_grids(gw_ctx* c, HostGrids& g) {
   c->tau = g.tau; c->x = g.x; c->w = g.w; c->nF = g.nF; c->nB = g.nB;
   c->TF = g.TF; c->TFp = g.TFp; c->TB = g.TB; c->TBp = g.TBp; c->rrow = g.rrow;
   std::vector<gwgrid::cd> wz(c->w.begin(), c->w.end());
@@ -401,6 +411,7 @@ gw_status gw_build_grids(gw_ctx* c, const long long* nF, const long long* nB) {
   c->dTF = c->dTFp = c->dTB = c->dTBp = c->dw = c->drrow = nullptr;
   c->dwF = nullptr;
   c->grids = false;
+  gw_status s;
   if ((s = upload(c, &c->dTF, c->TF.data(), c->TF.size() * 16)) != GW_OK) return s;
   if ((s = upload(c, &c->dTFp, c->TFp.data(), c->TFp.size() * 16)) != GW_OK) return s;
   if ((s = upload(c, &c->dTB, c->TB.data(), c->TB.size() * 16)) != GW_OK) return s;
@@ -412,11 +423,70 @@ gw_status gw_build_grids(gw_ctx* c, const long long* nF, const long long* nB) {
   return GW_OK;
 }
 
+gw_status gw_build_grids(gw_ctx* c, const long long* nF, const long long* nB) {
+  if (!c) return GW_ERR_ARG;
+  if (c->d.nw_f != c->d.ntau || c->d.nw_b != c->d.ntau + 1)
+    return fail(c, GW_ERR_ARG, "gw_build_grids needs nw_f = ntau and nw_b = ntau + 1");
+  HostGrids g;
+  std::string why;
+  gw_status s = make_grids(c->d.beta, c->d.ntau, nF, nB, g, why);
+  if (s != GW_OK) return fail(c, s, why);
+  return install_grids(c, g);
+}
+
+gw_status gw_set_grids(gw_ctx* c, const double* tau, const long long* nF, const long long* nB,
+                       const gw_z* TF, const gw_z* TFp, const gw_z* TB, const gw_z* TBp,
+                       const double* w) {
+  if (!c) return GW_ERR_ARG;
+  if (!tau || !nF || !nB || !TF || !TFp || !TB || !TBp || !w) return fail(c, GW_ERR_ARG, "NULL table");
+  const int nt = c->d.ntau, nwf = c->d.nw_f, nwb = c->d.nw_b;
+  const double beta = c->d.beta;
+  for (int i = 0; i < nt; ++i) {
+    if (!std::isfinite(tau[i]) || !(tau[i] > 0.0) || !(tau[i] < beta))
+      return fail(c, GW_ERR_ARG, "tau nodes must lie in (0, beta)");
+    if (i > 0 && !(tau[i] > tau[i - 1])) return fail(c, GW_ERR_ARG, "tau nodes must increase");
+    if (std::fabs(tau[nt - 1 - i] - (beta - tau[i])) > 1e-12 * beta)
+      return fail(c, GW_ERR_ARG, "tau nodes must be mirrored: tau[ntau-1-i] = beta - tau[i]");
+    if (!std::isfinite(w[i])) return fail(c, GW_ERR_ARG, "density row is not finite");
+  }
+  for (int n = 1; n < nwf; ++n)
+    if (nF[n] <= nF[n - 1]) return fail(c, GW_ERR_ARG, "nF must be strictly increasing");
+  for (int n = 1; n < nwb; ++n)
+    if (nB[n] <= nB[n - 1]) return fail(c, GW_ERR_ARG, "nB must be strictly increasing");
+  auto finite = [](const gw_z* a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(a[i].re) || !std::isfinite(a[i].im)) return false;
+    return true;
+  };
+  const size_t nfT = (size_t)nwf * nt, nbT = (size_t)nwb * nt;
+  if (!finite(TF, nfT) || !finite(TFp, nfT) || !finite(TB, nbT) || !finite(TBp, nbT))
+    return fail(c, GW_ERR_ARG, "transform table is not finite");
+  HostGrids g;
+  try {
+    g.tau.assign(tau, tau + nt);
+    g.x.resize(nt);
+    for (int i = 0; i < nt; ++i) g.x[i] = 2.0 * tau[i] / beta - 1.0;
+    g.w.assign(w, w + nt);
+    g.nF.assign(nF, nF + nwf);
+    g.nB.assign(nB, nB + nwb);
+    auto cz = [](const gw_z* a, size_t n) {
+      std::vector<gwgrid::cd> v(n);
+      for (size_t i = 0; i < n; ++i) v[i] = gwgrid::cd(a[i].re, a[i].im);
+      return v;
+    };
+    g.TF = cz(TF, nfT); g.TFp = cz(TFp, nfT); g.TB = cz(TB, nbT); g.TBp = cz(TBp, nbT);
+    finish_grids(beta, g);
+  } catch (const std::exception& e) {
+    return fail(c, GW_ERR_ARG, e.what());
+  }
+  return install_grids(c, g);
+}
+
 gw_status gw_get_grids(const gw_ctx* cc, double* tau, long long* nF, long long* nB, gw_z* TF,
                        gw_z* TFp, gw_z* TB, gw_z* TBp, double* w) {
   gw_ctx* c = const_cast<gw_ctx*>(cc);
   if (!c) return GW_ERR_ARG;
-  if (!c->grids) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!c->grids) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (tau) std::memcpy(tau, c->tau.data(), c->tau.size() * 8);
   if (nF) std::memcpy(nF, c->nF.data(), c->nF.size() * 8);
   if (nB) std::memcpy(nB, c->nB.data(), c->nB.size() * 8);
@@ -428,25 +498,55 @@ gw_status gw_get_grids(const gw_ctx* cc, double* tau, long long* nF, long long* 
   return GW_OK;
 }
 
+// Bytes of the polarization / self-energy chains for a tau chunk: two
+// intermediates of tc x Nk x naux x nao^2 (plus complex64 copies of two G
+// arrays in mixed precision).
+static size_t chain_bytes(const gw_ctx* c, int tc) {
+  if (c->d.precision == GW_PREC_FP32)
+    return 2 * align256((size_t)tc * c->nk * c->sv * 8) + 2 * align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
+  return 2 * align256((size_t)tc * c->nk * c->sv * 16);
+}
+
+static size_t screened_bytes(const gw_ctx* c, int nq) {
+  return align256((size_t)nq * c->d.nw_b * c->d.naux * (size_t)c->d.naux * 16);
+}
+
+static size_t hf_bytes(const gw_ctx* c) {
+  return align256((size_t)c->nk * c->sv * 16) + align256((size_t)c->nk * c->n2 * 16) +
+         align256((size_t)c->d.naux * 16);
+}
+
+// Per-q polarization buffers of the whole-chain calls (gw_sigma per q,
+// gw_sigma_jvp, gw_sigma_vjp): two tau arrays and four frequency arrays of
+// naux^2 complex numbers, at the end of the workspace.
+static size_t perq_tau_bytes(const gw_ctx* c) {
+  return align256((size_t)c->d.ntau * c->d.naux * (size_t)c->d.naux * 16);
+}
+static size_t perq_w_bytes(const gw_ctx* c) { return screened_bytes(c, 1); }
+static size_t perq_bytes(const gw_ctx* c) { return 2 * perq_tau_bytes(c) + 4 * perq_w_bytes(c); }
+
+// Front region the sub-calls of the whole-chain calls use.
+static size_t sigma_front_bytes(const gw_ctx* c, int tc) {
+  return std::max({chain_bytes(c, tc), screened_bytes(c, 1), hf_bytes(c)});
+}
+
 size_t gw_workspace_bytes(const gw_ctx* c, int op, int tau_chunk) {
   if (!c) return 0;
-  const size_t z = 16;
   switch (op) {
     case GW_OP_DYSON_JVP:
-      return 2 * align256((size_t)c->d.nw_f * c->nk * c->n2 * z);
+      return 2 * align256((size_t)c->d.nw_f * c->nk * c->n2 * 16);
     case GW_OP_POLARIZATION:
     case GW_OP_SELF_ENERGY:
       if (tau_chunk < 1 || tau_chunk > c->d.ntau) return 0;
-      if (c->d.precision == GW_PREC_FP32)   // complex64 intermediates + complex64 copies of G
-        return 2 * align256((size_t)tau_chunk * c->nk * c->sv * 8) +
-               2 * align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
-      return 2 * align256((size_t)tau_chunk * c->nk * c->sv * z);
+      return chain_bytes(c, tau_chunk);
     case GW_OP_SCREENED_W:
       if (tau_chunk < 1) return 0;
-      return align256((size_t)tau_chunk * c->d.nw_b * c->d.naux * (size_t)c->d.naux * z);
+      return screened_bytes(c, tau_chunk);
     case GW_OP_HF:
-      return align256((size_t)c->nk * c->sv * z) + align256((size_t)c->nk * c->n2 * z) +
-             align256((size_t)c->d.naux * z);
+      return hf_bytes(c);
+    case GW_OP_SIGMA:
+      if (tau_chunk < 1 || tau_chunk > c->d.ntau) return 0;
+      return sigma_front_bytes(c, tau_chunk) + perq_bytes(c);
   }
   return 0;
 }
@@ -479,6 +579,7 @@ gw_status gw_mix(gw_ctx* c, long long n, double alpha, const gw_z* X, gw_z* Y, d
   if (maxdiff) {
     HIPCHK(c, hipMemcpyAsync(maxdiff, c->dpart + nblk, sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    if (!std::isfinite(*maxdiff)) return fail(c, GW_ERR_NONFINITE, "gw_mix: non-finite element");
   }
   return GW_OK;
 }
@@ -532,18 +633,26 @@ gw_status gw_synchronize(gw_ctx* c) {
 // contractions add each 512-element chunk of their K sum into fp64.
 static const int kMixedChunk = 512;
 
-// complex64 copy of G(tau) in the workspace (mixed precision only)
+// Scratch of one chain call: base pointer, bytes and tau chunk (the
+// context's workspace, or another region of device memory).
+struct Work {
+  char* base;
+  size_t bytes;
+  int tc;
+};
+static Work ctx_work(gw_ctx* c) { return Work{(char*)c->ws, c->ws_bytes, c->tc}; }
+
 // complex64 copy of G in slot 0 or 1 of the mixed-precision workspace
-static gw_status g_to_c64(gw_ctx* c, const gw_z* G, void** Gc, int slot = 0) {
-  const size_t off = 2 * align256((size_t)c->tc * c->nk * c->sv * 8) +
+static gw_status g_to_c64(gw_ctx* c, const Work& w, const gw_z* G, void** Gc, int slot = 0) {
+  const size_t off = 2 * align256((size_t)w.tc * c->nk * c->sv * 8) +
                      (size_t)slot * align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
-  *Gc = (char*)c->ws + off;
+  *Gc = w.base + off;
   HIPCHK(c, to_c64_launch((const double2*)G, (float2*)*Gc, (long long)c->d.ntau * c->nk * c->n2, c->st));
   return GW_OK;
 }
 
-static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Gb, int q0, int nq,
-                          gw_z* P0, bool accumulate, bool two_slot);
+static gw_status pol_impl(gw_ctx* c, const Work& w, const void* V, const gw_z* G, const gw_z* Gb,
+                          int q0, int nq, gw_z* P0, bool accumulate, bool two_slot);
 
 gw_status gw_set_hermitian(gw_ctx* c, int mode) {
   if (!c) return GW_ERR_ARG;
@@ -560,42 +669,44 @@ gw_status gw_set_mu_window(gw_ctx* c, double ne_tol) {
 }
 
 gw_status gw_polarization(gw_ctx* c, const void* V, const gw_z* G, int q0, int nq, gw_z* P0) {
-  return pol_impl(c, V, G, G, q0, nq, P0, false, false);
+  if (!c) return GW_ERR_ARG;
+  return pol_impl(c, ctx_work(c), V, G, G, q0, nq, P0, false, false);
 }
 
 gw_status gw_polarization2(gw_ctx* c, const void* V, const gw_z* Ga, const gw_z* Gb, int q0, int nq,
                            int accumulate, gw_z* P0) {
-  return pol_impl(c, V, Ga, Gb, q0, nq, P0, accumulate != 0, true);
+  if (!c) return GW_ERR_ARG;
+  return pol_impl(c, ctx_work(c), V, Ga, Gb, q0, nq, P0, accumulate != 0, true);
 }
 
 // G fills the tau slot (G^{k+q}(tau_i)), Gb the mirrored slot (G^k(tau_{ntau-1-i})).
-static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Gb, int q0, int nq,
-                          gw_z* P0, bool accumulate, bool two_slot) {
+static gw_status pol_impl(gw_ctx* c, const Work& w, const void* V, const gw_z* G, const gw_z* Gb,
+                          int q0, int nq, gw_z* P0, bool accumulate, bool two_slot) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built");
   if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
   if (nq == 0) return GW_OK;
   if (!V || !G || !Gb || !P0) return fail(c, GW_ERR_ARG, "NULL array");
-  const int tc = c->tc;
-  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_POLARIZATION, tc))
+  const int tc = w.tc;
+  if (!w.base || tc < 1 || tc > c->d.ntau || w.bytes < chain_bytes(c, tc))
     return fail(c, GW_ERR_WORKSPACE, "polarization workspace too small");
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv;
   const long long S = (long long)nk * sv;                // one tau slice of X or Zt
   const bool f32 = c->d.precision == GW_PREC_FP32;
   const size_t ez = f32 ? 8 : 16;                        // bytes of V / X / Zt / G elements
-  char* X = (char*)c->ws;
-  char* Z = (char*)c->ws + align256((size_t)tc * S * ez);
+  char* X = w.base;
+  char* Z = w.base + align256((size_t)tc * S * ez);
   const char* Vd = (const char*)V;
   const char* Gd = (const char*)G;
   const char* Gbd = (const char*)Gb;
   if (f32) {
     void* Gc = nullptr;
-    gw_status s = g_to_c64(c, G, &Gc);
+    gw_status s = g_to_c64(c, w, G, &Gc);
     if (s != GW_OK) return s;
     Gd = Gbd = (const char*)Gc;
     if (Gb != G) {
-      if ((s = g_to_c64(c, Gb, &Gc, 1)) != GW_OK) return s;
+      if ((s = g_to_c64(c, w, Gb, &Gc, 1)) != GW_OK) return s;
       Gbd = (const char*)Gc;
     }
   }
@@ -657,7 +768,7 @@ static gw_status pol_impl(gw_ctx* c, const void* V, const gw_z* G, const gw_z* G
 static gw_status transform(gw_ctx* c, int stat, const gw_z* Xin, long long batch, long long R,
                            gw_z* Xout, bool forward) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (stat != GW_FERMION && stat != GW_BOSON) return fail(c, GW_ERR_ARG, "stat must be 0 or 1");
   if (batch < 0 || R < 0 || batch > 65535 || R > 0x7fffffffLL)
     return fail(c, GW_ERR_ARG, "batch or R out of range");
@@ -692,7 +803,7 @@ gw_status gw_iw_to_tau(gw_ctx* c, int stat, const gw_z* X_iw, long long batch, l
 // ------------------------------------------------------------- Eq. tilde_P_omega
 gw_status gw_screened_W(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (nq < 0 || nq > c->nk) return fail(c, GW_ERR_ARG, "nq out of range");
   if (nq == 0) return GW_OK;
   if (!P0 || !Pt) return fail(c, GW_ERR_ARG, "NULL array");
@@ -756,7 +867,8 @@ gw_status gw_screened_W_phi(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt, double*
   // The LU of I - P0 is still packed in the workspace.  Weights of the
   // Matsubara sum: value at tau = 0 of the least-squares fit, i.e. the
   // beta^- row reversed (mirrored nodes) times TBp; real part, scaled by
-  // 1 / (2 Nk).  dred[0] is the accumulator, dred[1..nw_b] the weights.
+  // 1 / (2 Nk).  dred[1..nw_b] holds the weights, dphi the per-matrix terms
+  // and, after them, their sum.
   const int nt = c->d.ntau, nwb = c->d.nw_b;
   if (nwb + 1 > 2 * 1024 + 8) return fail(c, GW_ERR_ARG, "gw_screened_W_phi supports nw_b <= 2055");
   std::vector<double> up((size_t)nwb + 1, 0.0);
@@ -766,9 +878,10 @@ gw_status gw_screened_W_phi(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt, double*
     up[1 + n] = r / (2.0 * c->nk);
   }
   HIPCHK(c, hipMemcpyAsync(c->dred, up.data(), up.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, phi_terms_launch((const double2*)c->ws, (const double2*)P0, c->d.naux,
-                             (long long)nq * nwb, c->dred + 1, nwb, c->dred, c->st));
-  HIPCHK(c, hipMemcpyAsync(phi, c->dred, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  const long long nmat = (long long)nq * nwb;
+  HIPCHK(c, phi_terms_launch((const double2*)c->ws, (const double2*)P0, c->d.naux, nmat, c->dred + 1,
+                             nwb, c->dphi, c->dphi + nmat, c->st));
+  HIPCHK(c, hipMemcpyAsync(phi, c->dphi + nmat, sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   return GW_OK;
 }
@@ -777,7 +890,7 @@ gw_status gw_screened_W_phi(gw_ctx* c, const gw_z* P0, int nq, gw_z* Pt, double*
 gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt, int q0, int nq,
                          gw_z* Sig) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
   if (nq == 0) return GW_OK;
   if (!V || !G || !Pt || !Sig) return fail(c, GW_ERR_ARG, "NULL array");
@@ -795,7 +908,7 @@ gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt
   const char* Gd = (const char*)G;
   if (f32) {
     void* Gc = nullptr;
-    gw_status s = g_to_c64(c, G, &Gc);
+    gw_status s = g_to_c64(c, ctx_work(c), G, &Gc);
     if (s != GW_OK) return s;
     Gd = (const char*)Gc;
   }
@@ -880,7 +993,7 @@ static gw_status gamma_of(gw_ctx* c, const gw_z* G, double2* gamma) {
 
 gw_status gw_density(gw_ctx* c, const gw_z* G, const gw_z* S, gw_z* gamma, double* n_out) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (!G || !gamma || (n_out && !S)) return fail(c, GW_ERR_ARG, "NULL array");
   gw_status s = gamma_of(c, G, (double2*)gamma);
   if (s != GW_OK || !n_out) return s;
@@ -894,7 +1007,7 @@ gw_status gw_density(gw_ctx* c, const gw_z* G, const gw_z* S, gw_z* gamma, doubl
 // ------------------------------------------------------------- Eqs. HF_J, HF_K
 gw_status gw_hf(gw_ctx* c, const void* V, const gw_z* G, gw_z* gamma_out, gw_z* Sinf) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (!V || !G || !Sinf) return fail(c, GW_ERR_ARG, "NULL array");
   if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_HF, 1))
     return fail(c, GW_ERR_WORKSPACE, "HF workspace too small");
@@ -964,7 +1077,7 @@ gw_status gw_hf(gw_ctx* c, const void* V, const gw_z* G, gw_z* gamma_out, gw_z* 
 gw_status gw_dyson_G(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf, const gw_z* Siw,
                      double mu, gw_z* G) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (!H0 || !S || !G) return fail(c, GW_ERR_ARG, "NULL array");
   if (!std::isfinite(mu)) return fail(c, GW_ERR_ARG, "mu is not finite");
   HIPCHK(c, zero_flag_launch(c->dflag, c->st));
@@ -981,7 +1094,7 @@ gw_status gw_find_mu(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf,
                      double n_target, double tol, double* mu_inout, gw_z* G_iw, gw_z* G_tau,
                      double* n_out) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (!H0 || !S || !mu_inout) return fail(c, GW_ERR_ARG, "NULL array");
   if (G_tau && !G_iw) return fail(c, GW_ERR_ARG, "G_tau needs G_iw");
   if (!(n_target > 0.0) || !(n_target < (double)c->d.ns * c->d.nao))
@@ -1020,6 +1133,7 @@ gw_status gw_find_mu(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf,
       if (m < target) lo = mid; else hi = mid;
       ++it;
     }
+    if (hi - lo > tol) return fail(c, GW_ERR_NOCONV, "mu search: bracket not narrowed to tol");
     *out = 0.5 * (lo + hi);
     return GW_OK;
   };
@@ -1061,13 +1175,13 @@ gw_status gw_find_mu(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf,
 // calls that never read V run in either precision
 static gw_status need_grids(gw_ctx* c) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   return GW_OK;
 }
 
 static gw_status need_fp64(gw_ctx* c) {
   if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "gw_build_grids has not run");
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
   if (c->d.precision != GW_PREC_FP64) return fail(c, GW_ERR_ARG, "derivatives need a GW_PREC_FP64 context");
   return GW_OK;
 }
@@ -1486,6 +1600,171 @@ gw_status gw_dyson_jvp(gw_ctx* c, const gw_z* S, const gw_z* G_iw, const gw_z* d
   }
   if (dmu) *dmu = m;
   return GW_OK;
+}
+
+// =========================================================================
+// Whole-chain calls: one Sigma[G] + Pi evaluation and its JVP / VJP, the
+// composition of the calls above (Sec. III, Algorithm 1).
+// =========================================================================
+
+// Per-q buffers at the end of the workspace (the front is left to the
+// sub-calls): two tau arrays and four frequency arrays of naux^2 numbers.
+struct PerQ {
+  gw_z *ta, *tb, *w0, *w1, *w2, *w3;
+};
+
+static gw_status perq_bufs(gw_ctx* c, PerQ& p) {
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_SIGMA, c->tc))
+    return fail(c, GW_ERR_WORKSPACE, "workspace too small for the whole-chain calls (GW_OP_SIGMA)");
+  char* b = (char*)c->ws + ((c->ws_bytes - perq_bytes(c)) & ~size_t(255));
+  const size_t tb = perq_tau_bytes(c), wb = perq_w_bytes(c);
+  p.ta = (gw_z*)b;
+  p.tb = (gw_z*)(b + tb);
+  p.w0 = (gw_z*)(b + 2 * tb);
+  p.w1 = (gw_z*)(b + 2 * tb + wb);
+  p.w2 = (gw_z*)(b + 2 * tb + 2 * wb);
+  p.w3 = (gw_z*)(b + 2 * tb + 3 * wb);
+  return GW_OK;
+}
+
+static gw_status zero_z(gw_ctx* c, gw_z* Y, long long n) {
+  HIPCHK(c, axpby_launch(n, 0.0, 0.0, nullptr, 0.0, 0.0, (double2*)Y, c->st));
+  return GW_OK;
+}
+
+// P~^q of G rebuilt for one q: P0^q(tau) -> P0^q(i Omega) (p.w0) ->
+// P~^q(i Omega) (p.w1) -> P~^q(tau) (p.ta).  phi (may be NULL) accumulates
+// this q's Phi~ term.
+static gw_status pt_one_q(gw_ctx* c, const void* V, const gw_z* G, int q, const PerQ& p, double* phi) {
+  gw_status s;
+  if ((s = pol_impl(c, ctx_work(c), V, G, G, q, 1, p.ta, false, false)) != GW_OK) return s;
+  if ((s = gw_tau_to_iw(c, GW_BOSON, p.ta, 1, (long long)c->d.naux * c->d.naux, p.w0)) != GW_OK) return s;
+  if (phi) {
+    double f = 0.0;
+    if ((s = gw_screened_W_phi(c, p.w0, 1, p.w1, &f)) != GW_OK) return s;
+    *phi += f;
+  } else if ((s = gw_screened_W(c, p.w0, 1, p.w1)) != GW_OK) {
+    return s;
+  }
+  return gw_iw_to_tau(c, GW_BOSON, p.w1, 1, (long long)c->d.naux * c->d.naux, p.ta);
+}
+
+gw_status gw_sigma(gw_ctx* c, const void* V, const gw_z* G, gw_z* gamma, gw_z* Sinf, gw_z* Stau,
+                   gw_z* P_tau, gw_z* P0_iw, gw_z* Pt_iw, double* phi) {
+  if (!c) return GW_ERR_ARG;
+  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
+  if (!V || !G || !Sinf || !Stau) return fail(c, GW_ERR_ARG, "NULL array");
+  const bool stored = P_tau || P0_iw || Pt_iw;
+  if (stored && !(P_tau && P0_iw && Pt_iw))
+    return fail(c, GW_ERR_ARG, "P_tau, P0_iw and Pt_iw are given all together or not at all");
+  if (phi) *phi = 0.0;
+  const int nk = c->nk, naux = c->d.naux;
+  const long long nn = (long long)naux * naux;
+  PerQ p{};
+  gw_status s;
+  if (!stored && (s = perq_bufs(c, p)) != GW_OK) return s;
+  if ((s = gw_hf(c, V, G, gamma, Sinf)) != GW_OK) return s;
+  if ((s = zero_z(c, Stau, (long long)c->d.ntau * nk * c->n2)) != GW_OK) return s;
+  double ph = 0.0;
+  if (stored) {
+    if ((s = pol_impl(c, ctx_work(c), V, G, G, 0, nk, P_tau, false, false)) != GW_OK) return s;
+    if ((s = gw_tau_to_iw(c, GW_BOSON, P_tau, nk, nn, P0_iw)) != GW_OK) return s;
+    // screened-interaction solves in q-batches as large as the workspace holds
+    const size_t per = screened_bytes(c, 1);
+    const int qb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, c->ws_bytes / per));
+    for (int q0 = 0; q0 < nk; q0 += qb) {
+      const int nq = std::min(qb, nk - q0);
+      const size_t off = (size_t)q0 * c->d.nw_b * nn;
+      if (phi) {
+        double f = 0.0;
+        if ((s = gw_screened_W_phi(c, P0_iw + off, nq, Pt_iw + off, &f)) != GW_OK) return s;
+        ph += f;
+      } else if ((s = gw_screened_W(c, P0_iw + off, nq, Pt_iw + off)) != GW_OK) {
+        return s;
+      }
+    }
+    if ((s = gw_iw_to_tau(c, GW_BOSON, Pt_iw, nk, nn, P_tau)) != GW_OK) return s;
+    if ((s = gw_self_energy(c, V, G, P_tau, 0, nk, Stau)) != GW_OK) return s;
+  } else {
+    for (int q = 0; q < nk; ++q) {
+      if ((s = pt_one_q(c, V, G, q, p, phi ? &ph : nullptr)) != GW_OK) return s;
+      if ((s = gw_self_energy(c, V, G, p.ta, q, 1, Stau)) != GW_OK) return s;
+    }
+  }
+  if (phi) {
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    *phi = ph;
+  }
+  return GW_OK;
+}
+
+// Shared checks of the derivative calls; sets *stored.
+static gw_status deriv_args(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt_tau,
+                            const gw_z* Pt_iw, bool* stored) {
+  if (!V || !G) return fail(c, GW_ERR_ARG, "NULL array");
+  if (!Pt_tau != !Pt_iw) return fail(c, GW_ERR_ARG, "Pt_tau and Pt_iw are given together or not at all");
+  *stored = Pt_tau != nullptr;
+  return GW_OK;
+}
+
+gw_status gw_sigma_jvp(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt_tau, const gw_z* Pt_iw,
+                       const gw_z* dG, gw_z* dSinf, gw_z* dStau) {
+  gw_status s = need_grids(c);
+  if (s != GW_OK) return s;
+  bool stored = false;
+  if ((s = deriv_args(c, V, G, Pt_tau, Pt_iw, &stored)) != GW_OK) return s;
+  if (!dG || !dSinf || !dStau) return fail(c, GW_ERR_ARG, "NULL array");
+  PerQ p{};
+  if ((s = perq_bufs(c, p)) != GW_OK) return s;
+  const int nk = c->nk, nt = c->d.ntau, nwb = c->d.nw_b;
+  const long long nn = (long long)c->d.naux * c->d.naux;
+  // dSigma_inf = HF[gamma(dG)] (linear in G)
+  if ((s = gw_hf(c, V, dG, nullptr, dSinf)) != GW_OK) return s;
+  if ((s = zero_z(c, dStau, (long long)nt * nk * c->n2)) != GW_OK) return s;
+  for (int q = 0; q < nk; ++q) {
+    const gw_z* pt = stored ? Pt_tau + (size_t)q * nt * nn : p.ta;
+    const gw_z* pw = stored ? Pt_iw + (size_t)q * nwb * nn : p.w1;
+    if (!stored && (s = pt_one_q(c, V, G, q, p, nullptr)) != GW_OK) return s;
+    // dP0 = P0[dG, G] + P0[G, dG]
+    if ((s = pol_impl(c, ctx_work(c), V, dG, G, q, 1, p.tb, false, true)) != GW_OK) return s;
+    if ((s = pol_impl(c, ctx_work(c), V, G, dG, q, 1, p.tb, true, true)) != GW_OK) return s;
+    // dP~(i Omega) = (I + P~) dP0(i Omega) (I + P~)
+    if ((s = gw_tau_to_iw(c, GW_BOSON, p.tb, 1, nn, p.w2)) != GW_OK) return s;
+    if ((s = gw_screened_W_lin(c, pw, p.w2, 1, 0, p.w3)) != GW_OK) return s;
+    if ((s = gw_iw_to_tau(c, GW_BOSON, p.w3, 1, nn, p.tb)) != GW_OK) return s;
+    // dSigma~ += Sigma~[dP~, G] + Sigma~[P~, dG]
+    if ((s = gw_self_energy(c, V, G, p.tb, q, 1, dStau)) != GW_OK) return s;
+    if ((s = gw_self_energy(c, V, dG, pt, q, 1, dStau)) != GW_OK) return s;
+  }
+  return GW_OK;
+}
+
+gw_status gw_sigma_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt_tau, const gw_z* Pt_iw,
+                       const gw_z* Sinf_bar, const gw_z* Stau_bar, gw_z* G_bar) {
+  gw_status s = need_fp64(c);
+  if (s != GW_OK) return s;
+  bool stored = false;
+  if ((s = deriv_args(c, V, G, Pt_tau, Pt_iw, &stored)) != GW_OK) return s;
+  if (!Sinf_bar || !Stau_bar || !G_bar) return fail(c, GW_ERR_ARG, "NULL array");
+  PerQ p{};
+  if ((s = perq_bufs(c, p)) != GW_OK) return s;
+  const int nk = c->nk, nt = c->d.ntau, nwb = c->d.nw_b;
+  const long long nn = (long long)c->d.naux * c->d.naux;
+  if ((s = zero_z(c, G_bar, (long long)nt * nk * c->n2)) != GW_OK) return s;
+  for (int q = 0; q < nk; ++q) {
+    const gw_z* pt = stored ? Pt_tau + (size_t)q * nt * nn : p.ta;
+    const gw_z* pw = stored ? Pt_iw + (size_t)q * nwb * nn : p.w1;
+    if (!stored && (s = pt_one_q(c, V, G, q, p, nullptr)) != GW_OK) return s;
+    // Sigma~ = SE[P~, G]: G part into G_bar, P~ part into P_bar (p.tb)
+    if ((s = gw_self_energy_vjp(c, V, G, pt, Stau_bar, q, 1, G_bar, p.tb)) != GW_OK) return s;
+    // back through i Omega -> tau, the screened-interaction solve, tau -> i Omega
+    if ((s = gw_transform_adjoint(c, GW_BOSON, 1, p.tb, 1, nn, p.w2)) != GW_OK) return s;
+    if ((s = gw_screened_W_lin(c, pw, p.w2, 1, 1, p.w3)) != GW_OK) return s;
+    if ((s = gw_transform_adjoint(c, GW_BOSON, 0, p.w3, 1, nn, p.tb)) != GW_OK) return s;
+    // both G slots of the polarization
+    if ((s = gw_polarization_vjp(c, V, G, p.tb, q, 1, G_bar)) != GW_OK) return s;
+  }
+  return gw_hf_vjp(c, V, Sinf_bar, G_bar);
 }
 
 }  // extern "C"

@@ -122,13 +122,14 @@ hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, i
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st);
 // P[b] <- (P[b] + P[b]^H) / 2 for b < nmat (n x n, row-major).
 hipError_t herm_avg_launch(double2* P, int n, long long nmat, hipStream_t st);
+// Eq. tilde_Phi_GW: for each of nmat matrices m of an LU-factorised I - P0
+// (packed in LU, U on and above the diagonal) writes
+// part[m] = wts[m % nw] (sum_i ln|U_ii| + Re tr P0_m), then out[0] = sum_m part[m]
+// in a fixed order.
+hipError_t phi_terms_launch(const double2* LU, const double2* P0, int n, long long nmat,
+                            const double* wts, int nw, double* part, double* out, hipStream_t st);
 // Finite-size corrections: Out[b] += alpha S[b % nk] X[b] S[b % nk] for
 // b < nmat (nk S matrices, nmat X and Out matrices, all n x n, n <= 64).
-// Eq. tilde_Phi_GW: for each of nmat matrices m of an LU-factorised I - P0
-// (packed in LU, U on and above the diagonal) adds
-// wts[m % nw] (sum_i ln|U_ii| + Re tr P0_m) to *acc.
-hipError_t phi_terms_launch(const double2* LU, const double2* P0, int n, long long nmat,
-                            const double* wts, int nw, double* acc, hipStream_t st);
 hipError_t sxs_add_launch(const double2* S, const double2* X, double2* Out, int n, int nk,
                           long long nmat, double alpha, hipStream_t st);
 hipError_t wlu_launch(int which, const double2* P0, double2* A, double2* B, int n, int j0, int nb,

@@ -803,9 +803,11 @@ hipError_t sxs_add_launch(const double2* S, const double2* X, double2* Out, int 
 }
 
 // Eq. tilde_Phi_GW: one wave per matrix; lanes stride over the diagonal,
-// a butterfly reduction sums the wave, lane 0 adds the weighted term.
+// a butterfly reduction sums the wave, lane 0 writes the weighted term of
+// its matrix.  The terms are then summed by sum_k in a fixed order, so the
+// result does not depend on the order in which the waves finish.
 __global__ void __launch_bounds__(64) phi_terms_k(const double2* LU, const double2* P0, int n,
-                                                  const double* wts, int nw, double* acc) {
+                                                  const double* wts, int nw, double* part) {
   const size_t m = blockIdx.x;
   const size_t nn = (size_t)n * (size_t)n;
   const double2* A = LU + m * nn;
@@ -816,15 +818,17 @@ __global__ void __launch_bounds__(64) phi_terms_k(const double2* LU, const doubl
     s += log(hypot(u.x, u.y)) + P[(size_t)i * n + i].x;
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (threadIdx.x == 0) atomicAdd(acc, wts[m % (size_t)nw] * s);
+  if (threadIdx.x == 0) part[m] = wts[m % (size_t)nw] * s;
 }
 
 hipError_t phi_terms_launch(const double2* LU, const double2* P0, int n, long long nmat,
-                            const double* wts, int nw, double* acc, hipStream_t st) {
+                            const double* wts, int nw, double* part, double* out, hipStream_t st) {
   if (n <= 0 || nmat <= 0) return hipSuccess;
   if (nw <= 0 || nmat > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  phi_terms_k<<<dim3((unsigned)nmat, 1, 1), 64, 0, st>>>(LU, P0, n, wts, nw, acc);
-  return hipGetLastError();
+  phi_terms_k<<<dim3((unsigned)nmat, 1, 1), 64, 0, st>>>(LU, P0, n, wts, nw, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return sum_launch(part, nmat, 1.0, out, st);
 }
 
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st) {
@@ -1032,7 +1036,12 @@ hipError_t trace_launch(const double2* g, const double2* S, int n, int nk, doubl
   return hipGetLastError();
 }
 
-// Y = (1 - alpha) Y + alpha X (X may be null); per-block max |X - Y_old| into part.
+// max that propagates NaN: fmax drops a NaN operand, which would let a
+// corrupted vector report a finite (even zero) largest difference.
+__device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+
+// Y = (1 - alpha) Y + alpha X (X may be null); per-block max |X - Y_old| into part
+// (NaN if any difference is NaN, e.g. a NaN element or Inf - Inf).
 __global__ void __launch_bounds__(256) mix_k(long long n, double alpha, const double2* X, double2* Y,
                                               double* part) {
   __shared__ double s[256];
@@ -1046,7 +1055,7 @@ __global__ void __launch_bounds__(256) mix_k(long long n, double alpha, const do
     } else {
       y = Y[i];
       const double dx = x.x - y.x, dy = x.y - y.y;
-      mx = fmax(mx, sqrt(dx * dx + dy * dy));
+      mx = nan_max(mx, sqrt(dx * dx + dy * dy));
     }
     Y[i] = double2{y.x + alpha * (x.x - y.x), y.y + alpha * (x.y - y.y)};
   }
@@ -1054,7 +1063,7 @@ __global__ void __launch_bounds__(256) mix_k(long long n, double alpha, const do
   s[threadIdx.x] = mx;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+    if ((int)threadIdx.x < h) s[threadIdx.x] = nan_max(s[threadIdx.x], s[threadIdx.x + h]);
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
@@ -1063,11 +1072,11 @@ __global__ void __launch_bounds__(256) mix_k(long long n, double alpha, const do
 __global__ void __launch_bounds__(256) max_k(const double* x, int n, double* out) {
   __shared__ double s[256];
   double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, x[i]);
+  for (int i = threadIdx.x; i < n; i += 256) m = nan_max(m, x[i]);
   s[threadIdx.x] = m;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+    if ((int)threadIdx.x < h) s[threadIdx.x] = nan_max(s[threadIdx.x], s[threadIdx.x + h]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = s[0];

@@ -15,10 +15,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgw.so")
 
-GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPACE, GW_ERR_STATE = range(7)
+(GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPACE, GW_ERR_STATE,
+ GW_ERR_NONFINITE) = range(8)
 GW_FERMION, GW_BOSON = 0, 1
 GW_PREC_FP64, GW_PREC_FP32 = 0, 1
-GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF, GW_OP_DYSON_JVP = range(5)
+GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF, GW_OP_DYSON_JVP, GW_OP_SIGMA = range(6)
 KCLASS = dict(other=0, pol_contract=1, pol_producer=2, se_contract=3, se_producer=4,
               se_final=5, transform=6, hf=7, wdyson=8, dyson=9)
 
@@ -29,7 +30,8 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_polarization2", "gw_screened_W_lin", "gw_transform_adjoint", "gw_self_energy_vjp",
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
            "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
-           "gw_hermitize", "gw_set_mu_window", "gw_finite_size", "gw_screened_W_phi"]
+           "gw_hermitize", "gw_set_mu_window", "gw_finite_size", "gw_screened_W_phi",
+           "gw_set_grids", "gw_sigma", "gw_sigma_jvp", "gw_sigma_vjp"]
 
 
 class GwError(RuntimeError):
@@ -61,6 +63,10 @@ def load():
         "gw_destroy": ([P], I),
         "gw_build_grids": ([P, P, P], I),
         "gw_get_grids": ([P, P, P, P, P, P, P, P, P], I),
+        "gw_set_grids": ([P, P, P, P, P, P, P, P, P], I),
+        "gw_sigma": ([P, P, P, P, P, P, P, P, P, P], I),
+        "gw_sigma_jvp": ([P, P, P, P, P, P, P, P], I),
+        "gw_sigma_vjp": ([P, P, P, P, P, P, P, P], I),
         "gw_workspace_bytes": ([P, I, I], SZ),
         "gw_set_workspace": ([P, P, SZ, I], I),
         "gw_polarization": ([P, P, P, I, I, P], I),
@@ -142,7 +148,12 @@ class Context:
     """One library context: dimensions, grids, stream and workspace."""
 
     def __init__(self, mesh, nao, naux, ntau, beta, ns=2, nF=None, nB=None, tau_chunk=None,
-                 max_nq=None, stream=None, workspace_gb=None, precision="fp64"):
+                 max_nq=None, stream=None, workspace_gb=None, precision="fp64", grids=None):
+        """grids: None builds the Chebyshev tables in the library
+        (gw_build_grids with the Matsubara sets nF, nB or its own greedy
+        choice); or a dict with tau, nF, nB, TF, TFp, TB, TBp, w (numpy host
+        arrays, e.g. an intermediate-representation basis) installed with
+        gw_set_grids, whose shapes fix nw_f and nw_b."""
         import torch
         L = load()
         if precision not in ("fp64", "fp32"):
@@ -152,7 +163,10 @@ class Context:
         self.mesh = tuple(int(m) for m in mesh)
         self.nk = int(np.prod(self.mesh))
         self.nao, self.naux, self.ntau, self.beta, self.ns = int(nao), int(naux), int(ntau), float(beta), int(ns)
-        self.nw_f, self.nw_b = self.ntau, self.ntau + 1
+        if grids is None:
+            self.nw_f, self.nw_b = self.ntau, self.ntau + 1
+        else:
+            self.nw_f, self.nw_b = len(grids["nF"]), len(grids["nB"])
         d = Dims((ctypes.c_int * 3)(*self.mesh), self.nao, self.naux, self.ntau, self.nw_f,
                  self.nw_b, self.ns, GW_PREC_FP64 if precision == "fp64" else GW_PREC_FP32,
                  self.beta)
@@ -162,9 +176,12 @@ class Context:
         if st != GW_OK:
             raise GwError(st, "gw_create failed: " + L.gw_status_string(st).decode())
         self.h = h
-        nf = None if nF is None else (ctypes.c_longlong * self.nw_f)(*[int(x) for x in nF])
-        nb = None if nB is None else (ctypes.c_longlong * self.nw_b)(*[int(x) for x in nB])
-        self._check(L.gw_build_grids(self.h, nf, nb), "gw_build_grids")
+        if grids is None:
+            nf = None if nF is None else (ctypes.c_longlong * self.nw_f)(*[int(x) for x in nF])
+            nb = None if nB is None else (ctypes.c_longlong * self.nw_b)(*[int(x) for x in nB])
+            self._check(L.gw_build_grids(self.h, nf, nb), "gw_build_grids")
+        else:
+            self.set_grids(grids)
         # workspace: largest tau chunk that fits the budget (default 40% of free memory)
         free, _ = torch.cuda.mem_get_info()
         budget = int((workspace_gb * 2 ** 30) if workspace_gb else 0.4 * free)
@@ -175,6 +192,7 @@ class Context:
                 tau_chunk = (tau_chunk + 1) // 2
         self.tau_chunk = int(tau_chunk)
         need = max(L.gw_workspace_bytes(self.h, GW_OP_POLARIZATION, self.tau_chunk),
+                   L.gw_workspace_bytes(self.h, GW_OP_SIGMA, self.tau_chunk),
                    L.gw_workspace_bytes(self.h, GW_OP_SCREENED_W, self.max_nq),
                    L.gw_workspace_bytes(self.h, GW_OP_HF, 1),
                    L.gw_workspace_bytes(self.h, GW_OP_DYSON_JVP, 1))
@@ -190,6 +208,25 @@ class Context:
             L = load()
             raise GwError(st, f"{what}: {L.gw_status_string(st).decode()}: "
                               f"{L.gw_last_error(self.h).decode()}")
+
+    def set_grids(self, grids):
+        """Install host tables with gw_set_grids (see include/gw.h)."""
+        L = load()
+        nt, nf, nb = self.ntau, self.nw_f, self.nw_b
+        shapes = dict(tau=(nt,), nF=(nf,), nB=(nb,), TF=(nf, nt), TFp=(nt, nf), TB=(nb, nt),
+                      TBp=(nt, nb), w=(nt,))
+        types = dict(tau=np.float64, nF=np.int64, nB=np.int64, TF=np.complex128, TFp=np.complex128,
+                     TB=np.complex128, TBp=np.complex128, w=np.float64)
+        arr = {}
+        for k, shp in shapes.items():
+            a = np.ascontiguousarray(np.asarray(grids[k]), dtype=types[k])
+            if a.shape != shp:
+                raise ValueError(f"grids[{k!r}] has shape {a.shape}, expected {shp}")
+            arr[k] = a
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._check(L.gw_set_grids(self.h, p(arr["tau"]), p(arr["nF"]), p(arr["nB"]), p(arr["TF"]),
+                                   p(arr["TFp"]), p(arr["TB"]), p(arr["TBp"]), p(arr["w"])),
+                    "gw_set_grids")
 
     def get_grids(self):
         L = load()
@@ -337,6 +374,42 @@ def gw_self_energy(ctx, V, G_tau, Pt_tau, q0, nq, Sig_tau):
         ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
         _ptr(Pt_tau, "Pt_tau", (nq, ctx.ntau, ctx.naux, ctx.naux)), int(q0), int(nq),
         _ptr(Sig_tau, "Sig_tau", ctx.g_shape())), "gw_self_energy")
+
+
+def gw_sigma(ctx, V, G_tau, Sig_inf, Sig_tau, gamma=None, P_tau=None, P0_iw=None, Pt_iw=None,
+             want_phi=False):
+    """One Sigma[G] + Pi evaluation (gw_sigma): Sig_inf, Sig_tau overwritten;
+    with P_tau, P0_iw, Pt_iw ([Nk][ntau|nw_b][naux][naux]) P~ is kept there,
+    else the chain runs q by q.  Returns Phi~ when want_phi, else None."""
+    pt, pw = (ctx.nk, ctx.ntau, ctx.naux, ctx.naux), (ctx.nk, ctx.nw_b, ctx.naux, ctx.naux)
+    phi = ctypes.c_double(0.0)
+    ctx._check(load().gw_sigma(
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        _ptr(gamma, "gamma", ctx.k_shape()), _ptr(Sig_inf, "Sig_inf", ctx.k_shape()),
+        _ptr(Sig_tau, "Sig_tau", ctx.g_shape()), _ptr(P_tau, "P_tau", pt), _ptr(P0_iw, "P0_iw", pw),
+        _ptr(Pt_iw, "Pt_iw", pw), ctypes.byref(phi) if want_phi else None), "gw_sigma")
+    return phi.value if want_phi else None
+
+
+def gw_sigma_jvp(ctx, V, G_tau, Pt_tau, Pt_iw, dG_tau, dSig_inf, dSig_tau):
+    """dSig = J dG of G -> (Sigma_inf, Sigma~); Pt_tau, Pt_iw from gw_sigma, or
+    None (P~ rebuilt per q)."""
+    pt, pw = (ctx.nk, ctx.ntau, ctx.naux, ctx.naux), (ctx.nk, ctx.nw_b, ctx.naux, ctx.naux)
+    ctx._check(load().gw_sigma_jvp(
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        _ptr(Pt_tau, "Pt_tau", pt), _ptr(Pt_iw, "Pt_iw", pw), _ptr(dG_tau, "dG_tau", ctx.g_shape()),
+        _ptr(dSig_inf, "dSig_inf", ctx.k_shape()), _ptr(dSig_tau, "dSig_tau", ctx.g_shape())),
+        "gw_sigma_jvp")
+
+
+def gw_sigma_vjp(ctx, V, G_tau, Pt_tau, Pt_iw, Sinf_bar, Stau_bar, G_bar):
+    """G_bar = J^H (Sinf_bar, Stau_bar) (torch's complex-gradient convention)."""
+    pt, pw = (ctx.nk, ctx.ntau, ctx.naux, ctx.naux), (ctx.nk, ctx.nw_b, ctx.naux, ctx.naux)
+    ctx._check(load().gw_sigma_vjp(
+        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        _ptr(Pt_tau, "Pt_tau", pt), _ptr(Pt_iw, "Pt_iw", pw),
+        _ptr(Sinf_bar, "Sinf_bar", ctx.k_shape()), _ptr(Stau_bar, "Stau_bar", ctx.g_shape()),
+        _ptr(G_bar, "G_bar", ctx.g_shape())), "gw_sigma_vjp")
 
 
 def gw_density(ctx, G_tau, S, gamma, want_count=True):

@@ -59,21 +59,16 @@ class GWPath:
     # ------------------------------------------------ Sigma[G] + Pi -----
     def sigma(self, G_tau, out_inf=None, out_tau=None):
         """Sigma_inf[G] (Eqs. HF_J, HF_K) and Sigma~[G](tau) (Eqs. tilde_P0_tau ...
-        tilde_sigma2), all q at once."""
+        tilde_sigma2), all q at once (gw_sigma); P~(tau) and P~(i Omega) of G
+        stay in self.P0 and self.Pw."""
         c = self.ctx
         out_inf = self.new_inf if out_inf is None else out_inf
         out_tau = self.new_tau if out_tau is None else out_tau
-        gw.gw_hf(c, self.V, G_tau, self.gamma, out_inf)
         gw.gw_set_hermitian(c, self.hermitian)         # the context may be shared
-        gw.gw_polarization(c, self.V, G_tau, 0, c.nk, self.P0)
-        gw.gw_tau_to_iw(c, gw.GW_BOSON, self.P0, self.P0w, batch=c.nk)
+        phi = gw.gw_sigma(c, self.V, G_tau, out_inf, out_tau, gamma=self.gamma, P_tau=self.P0,
+                          P0_iw=self.P0w, Pt_iw=self.Pw, want_phi=self.want_phi)
         if self.want_phi:
-            self.phi = gw.gw_screened_W_phi(c, self.P0w, self.Pw)
-        else:
-            gw.gw_screened_W(c, self.P0w, self.Pw)
-        gw.gw_iw_to_tau(c, gw.GW_BOSON, self.Pw, self.P0, batch=c.nk)
-        gw.gw_mix(c, 1.0, None, out_tau)                     # zero before accumulating
-        gw.gw_self_energy(c, self.V, G_tau, self.P0, 0, c.nk, out_tau)
+            self.phi = phi
         if self.finite_size is not None:
             chi, head = self.finite_size
             gw.gw_finite_size(c, self.S, chi, self.gamma, out_inf, G_tau, head, out_tau)

@@ -26,13 +26,15 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = gw.load()
-    for s in range(7):
+    for s in range(8):
         assert L.gw_status_string(s)
+    assert L.gw_status_string(gw.GW_ERR_NONFINITE) == b"non-finite value"
     assert L.gw_status_string(2) == b"HIP runtime error"
 
 
 @pytest.mark.parametrize("field,value", [("nao", 0), ("nao", 61), ("ntau", 7), ("ns", 3),
-                                         ("nw_f", 5), ("nw_b", 10), ("beta", -1.0),
+                                         ("nw_f", 5), ("nw_b", 10), ("nw_f", 97), ("nw_b", 98),
+                                         ("beta", -1.0),
                                          ("naux", 0), ("precision", 9)])
 def test_create_rejects_bad_dims_without_gpu(field, value):
     L = gw.load()
@@ -50,8 +52,11 @@ def test_create_rejects_null():
     assert L.gw_destroy(None) == gw.GW_ERR_ARG
 
 
-@pytest.mark.parametrize("beta,ntau", [(50.0, 24), (20.0, 20), (100.0, 60)])
+@pytest.mark.parametrize("beta,ntau", [(50.0, 24), (20.0, 20), (100.0, 60), (100.0, 100),
+                                       (200.0, 120)])
 def test_host_grids_match_oracle(beta, ntau):
+    """(100, 100) and (200, 120) are the grids of the si-4x4x4 and si-5x5x5
+    workloads."""
     p = gw.gw_grids_host(beta, ntau)
     o = og.Grids(beta, ntau)
     assert np.array_equal(p["nF"], o.nF) and np.array_equal(p["nB"], o.nB)

@@ -187,3 +187,35 @@ def test_mixed_precision_newton_krylov():
     assert rel(b[0], a[0]) < 1e-5 and rel(b[1], a[1]) < 1e-5
     assert b[4] < 1e-8
     assert np.abs(b[2] - a[2]).max() < 1e-6 and np.abs(b[3] - a[3]).max() < 1e-6
+
+
+def test_diis_fixed_point_matches_oracle_scgw():
+    """DIIS's self-consistent Sigma against the oracle's own damped scGW
+    iteration (reading R10) run to its fixed point on the CPU."""
+    from oracle import grids as og
+    from oracle import gw as ogw
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.diis import DIIS
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(mesh=(2, 2, 1), nao=4, naux=12, ntau=12, beta=10.0, seed=31, n_target=4.0)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    g = og.Grids(wl.beta, wl.ntau)
+    hist = ogw.scgw(H0, S, V, g, wl.mesh, NS, wl.n_target, n_iter=120)
+    (mu_a, si_a, st_a, _), (mu_r, si_r, st_r, _) = hist[-2], hist[-1]
+    last = max(np.abs(si_r - si_a).max(), np.abs(st_r - st_a).max())
+    print(f"oracle damped scGW: last change {last:.2e}, mu {mu_r:.12f}")
+    assert last < 1e-11
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS)
+    try:
+        path = GWPath(ctx, dev(V), dev(H0), dev(S), wl.n_target)
+        st = path.start(0.0)
+        dz = DIIS(path, depth=6)
+        x, F = dz.solve(st.sig_inf, st.sig_tau, st.mu, tol=1e-11, max_iter=60)
+        d_inf = np.abs(dz.inf(x).cpu().numpy() - si_r).max()
+        d_tau = np.abs(dz.tau(x).cpu().numpy() - st_r).max()
+        print(f"DIIS vs oracle fixed point: |dSigma_inf| {d_inf:.2e} |dSigma~| {d_tau:.2e} "
+              f"mu {dz.mu:.12f} ({dz.stats.evaluations} evaluations)")
+        assert dz.stats.residuals[-1] < 1e-11
+        assert d_inf < 1e-9 and d_tau < 1e-9 and abs(dz.mu - mu_r) < 1e-9
+    finally:
+        ctx.close()

@@ -357,6 +357,62 @@ def test_invariants():
             assert np.linalg.eigvalsh(ah).max() < 1e-12
 
 
+def _time_reversal_symmetric(wl, H0, V):
+    """H0(-k) = H0(k)^*, V^{-k1,-k2}(Q) = V^{k1,k2}(Q)^* (time reversal), keeping
+    V^{k2,k1}(Q) = V^{k1,k2}(Q)^dagger: average over the group generated by the
+    two involutions."""
+    plus, minus = gw.mesh_tables(wl.mesh)
+    nk = wl.nk
+    neg = minus[:, 0]                                        # index of -k
+    H = H0.copy()
+    for k in range(nk):
+        if neg[k] == k:
+            H[k] = H0[k].real
+        elif k < neg[k]:
+            H[neg[k]] = np.conj(H0[k])
+    Vf = np.empty((nk, nk) + V.shape[2:], np.complex128)     # Vf[k1, k2] = V^{k1,k2}
+    for q in range(nk):
+        for k in range(nk):
+            Vf[k, plus[q, k]] = V[q, k]
+    dag = lambda X: np.conj(np.swapaxes(X, -1, -2))
+    A = dag(np.swapaxes(Vf, 0, 1))                           # (V^{k2,k1})^dagger
+    B = np.conj(Vf[np.ix_(neg, neg)])                        # conj V^{-k1,-k2}
+    AB = dag(np.swapaxes(B, 0, 1))
+    W = 0.25 * (Vf + A + B + AB)
+    V2 = np.empty_like(V)
+    for q in range(nk):
+        for k in range(nk):
+            V2[q, k] = W[k, plus[q, k]]
+    return H, V2
+
+
+def test_bosonic_symmetry_plain_form_with_time_reversal():
+    """Reading R14: with time-reversal-symmetric H0 and V the bubble obeys the
+    plain bosonic symmetry P0^q(beta - tau) = P0^q(tau); without time reversal
+    only the general identity P0^q(beta - tau) = [P0^{-q}(tau)]^T holds."""
+    wl, g, H0, S, V, G = _setup(mesh=(4, 2, 1), nao=3, naux=4, ntau=12, beta=10.0)
+    H, V2 = _time_reversal_symmetric(wl, H0, V)
+    plus, minus = gw.mesh_tables(wl.mesh)
+    neg = minus[:, 0]
+    # the construction keeps the pair relation and adds time reversal
+    for q in range(wl.nk):
+        for k in range(wl.nk):
+            k2 = plus[q, k]
+            q2 = minus[k2, k]                                 # slab of V^{k2,k}: k + q2 = k
+            assert np.abs(V2[q2, k2] - np.conj(np.swapaxes(V2[q, k], -1, -2))).max() < 1e-15
+            assert np.abs(V2[neg[q], neg[k]] - np.conj(V2[q, k])).max() < 1e-15
+    G2 = gw.g0_tau(H, S, 0.1, wl.beta, g.tau)
+    P_tr = gw.polarization(V2, G2, wl.mesh, NS)
+    P_gen = gw.polarization(V, G, wl.mesh, NS)
+    scale = np.abs(P_tr).max()
+    assert scale > 1e-3
+    assert np.abs(P_tr[:, ::-1] - P_tr).max() < 1e-14 * scale
+    # without time reversal the plain form fails and the general one holds
+    assert np.abs(P_gen[:, ::-1] - P_gen).max() > 1e-6 * np.abs(P_gen).max()
+    for q in range(wl.nk):
+        assert np.abs(P_gen[q, ::-1] - np.swapaxes(P_gen[neg[q]], -1, -2)).max() < 1e-15
+
+
 def test_momentum_shift_covariance():
     wl, g, H0, S, V, G = _setup(mesh=(3, 1, 1))
     plus, minus = gw.mesh_tables(wl.mesh)
