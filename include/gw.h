@@ -179,6 +179,23 @@ gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
 gw_status gw_polarization(gw_ctx* ctx, const void* V, const gw_z* G_tau, int q0, int nq,
                           gw_z* P0_tau);   /* V: gw_z (GW_PREC_FP64) or gw_c (GW_PREC_FP32) */
 
+/* gw_polarization for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result, with the chain's intermediates in a fixed scratch array of
+ * 128 MiB that the library holds on each GPU until the process ends, instead
+ * of the caller's workspace.  The call allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine, and no profiling events (launches
+ * made through it are not counted by gw_profile_read).  The tau chunk is the
+ * largest that fits the scratch; if one tau slice of the intermediates does
+ * not fit (fp64: 32 Nk naux nao^2 bytes > 128 MiB; fp32: 16 Nk naux nao^2 +
+ * 16 ntau Nk nao^2 bytes) the call returns GW_ERR_WORKSPACE and launches
+ * nothing.  Every call on one GPU shares that GPU's scratch, whatever the
+ * context: calls that overlap in time on one GPU (different streams or host
+ * threads) race and give undefined results.  Other arguments and errors as
+ * gw_polarization.                                                          */
+gw_status gw_polarization_noalloc(gw_ctx* ctx, const void* V, const gw_z* G_tau, int q0, int nq,
+                                  gw_z* P0_tau);
+
 /* Hermitian mode of the polarization (off after gw_create).  mode is a bit
  * set: GW_HERM_FORWARD states that every G_tau passed to gw_polarization is
  * Hermitian in its orbital indices at each tau and k (true of the Green's

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,17 @@
 #include "grids.h"
 #include "gw_kernels.h"
 
+// Fixed scratch for gw_polarization_noalloc: a file-scope device array, one
+// copy per GPU for the life of the process.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): the
+// device address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_dev.
+static const size_t kScratchBytes = size_t(128) << 20;   // 128 MiB
+static __device__ __align__(256) char scratch[kScratchBytes];
+static const int kMaxDevices = 64;
+static char* g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
 struct gw_ctx {
   gw_dims d;
   int nk = 0;
@@ -22,6 +34,7 @@ struct gw_ctx {
   long long sv = 0;      // complex elements of one V^{k,k+q} block: naux * nao^2
   hipStream_t st = nullptr;
   int device = 0;
+  char* scratch = nullptr;   // this device's copy of the fixed scratch array (see below)
   bool grids = false;
   std::vector<double> tau, x, w;
   std::vector<long long> nF, nB;
@@ -276,6 +289,17 @@ gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
   c->sv = (long long)d->naux * c->n2;
   c->st = (hipStream_t)hip_stream;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return GW_ERR_DEVICE; }
+  if (c->device < 0 || c->device >= kMaxDevices) { delete c; return GW_ERR_DEVICE; }
+  {
+    // once per device, with that device current: the device address of its scratch copy
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[c->device]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) { delete c; return GW_ERR_DEVICE; }
+      g_scratch_dev[c->device] = (char*)p;
+    }
+    c->scratch = g_scratch_dev[c->device];
+  }
   std::vector<int> plus((size_t)c->nk * c->nk), minus((size_t)c->nk * c->nk);
   const int* m = d->mesh;
   for (int q = 0; q < c->nk; ++q)
@@ -677,6 +701,27 @@ gw_status gw_polarization2(gw_ctx* c, const void* V, const gw_z* Ga, const gw_z*
                            int accumulate, gw_z* P0) {
   if (!c) return GW_ERR_ARG;
   return pol_impl(c, ctx_work(c), V, Ga, Gb, q0, nq, P0, accumulate != 0, true);
+}
+
+// gw_polarization on the fixed scratch array instead of the caller's
+// workspace: the largest tau chunk whose intermediates fit is used.  Makes
+// no allocation (profiling events are not recorded during the call).
+gw_status gw_polarization_noalloc(gw_ctx* c, const void* V, const gw_z* G, int q0, int nq, gw_z* P0) {
+  if (!c) return GW_ERR_ARG;
+  if (!c->scratch) return fail(c, GW_ERR_DEVICE, "scratch address not set up");
+  int tc = 0;
+  for (int t = c->d.ntau; t >= 1; t = (t == 1) ? 0 : (t + 1) / 2)
+    if (chain_bytes(c, t) <= kScratchBytes) { tc = t; break; }
+  if (tc == 0)
+    return fail(c, GW_ERR_WORKSPACE,
+                "gw_polarization_noalloc: one tau slice of the intermediates needs " +
+                    std::to_string(chain_bytes(c, 1)) + " bytes, above the fixed scratch of " +
+                    std::to_string(kScratchBytes) + " bytes");
+  const bool prof = c->prof;
+  c->prof = false;
+  const gw_status s = pol_impl(c, Work{c->scratch, kScratchBytes, tc}, V, G, G, q0, nq, P0, false, false);
+  c->prof = prof;
+  return s;
 }
 
 // G fills the tau slot (G^{k+q}(tau_i)), Gb the mirrored slot (G^k(tau_{ntau-1-i})).

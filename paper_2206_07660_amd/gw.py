@@ -31,7 +31,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
            "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
            "gw_hermitize", "gw_set_mu_window", "gw_finite_size", "gw_screened_W_phi",
-           "gw_set_grids", "gw_sigma", "gw_sigma_jvp", "gw_sigma_vjp"]
+           "gw_set_grids", "gw_sigma", "gw_sigma_jvp", "gw_sigma_vjp", "gw_polarization_noalloc"]
 
 
 class GwError(RuntimeError):
@@ -70,6 +70,7 @@ def load():
         "gw_workspace_bytes": ([P, I, I], SZ),
         "gw_set_workspace": ([P, P, SZ, I], I),
         "gw_polarization": ([P, P, P, I, I, P], I),
+        "gw_polarization_noalloc": ([P, P, P, I, I, P], I),
         "gw_set_hermitian": ([P, I], I),
         "gw_set_mu_window": ([P, D], I),
         "gw_finite_size": ([P, P, D, P, P, P, P, P], I),
@@ -317,6 +318,14 @@ def gw_polarization(ctx, V, G_tau, q0, nq, P0_tau):
         ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
         int(q0), int(nq),
         _ptr(P0_tau, "P0_tau", (nq, ctx.ntau, ctx.naux, ctx.naux))), "gw_polarization")
+
+
+def gw_polarization_noalloc(ctx, V, G_tau, q0, nq, P0_tau):
+    """gw_polarization on the library's fixed scratch (no allocation; see gw.h)."""
+    ctx._check(load().gw_polarization_noalloc(
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        int(q0), int(nq),
+        _ptr(P0_tau, "P0_tau", (nq, ctx.ntau, ctx.naux, ctx.naux))), "gw_polarization_noalloc")
 
 
 def _transform(fn, ctx, stat, Xin, Xout, batch, fwd):
