@@ -61,6 +61,55 @@ def load_traffic(kclass_name):
     return c.get("hbm_bytes_per_launch")
 
 
+def host_info():
+    """CPU model, logical CPU count and the BLAS numpy calls (vendor, threads)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
+    try:
+        import numpy  # noqa: F401  (loads the BLAS numpy links)
+        from threadpoolctl import threadpool_info
+        blas = [{k: i.get(k) for k in ("internal_api", "version", "num_threads")}
+                for i in threadpool_info() if i.get("user_api") == "blas"]
+    except Exception:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "blas": blas}
+
+
+def oracle_timings():
+    """The CPU oracle, as it stands, timed on whole Sigma+Pi evaluations
+    (oracle.gw.sigma_evaluation on the G0 of each workload): tiny-2x2x2 with
+    all BLAS threads and with one, ad-3x3x3 with all threads."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from paper_2206_07660_amd import inputs as inp
+    from oracle import grids as og
+    from oracle import gw as ogw
+    out = {"host": host_info(), "runs": []}
+    for name, threads in (("tiny-2x2x2", None), ("tiny-2x2x2", 1), ("ad-3x3x3", None)):
+        wl = inp.WORKLOADS[name]
+        g = og.Grids(wl.beta, wl.ntau)
+        H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+        G = ogw.g0_tau(H0, S, wl.mu0, wl.beta, g.tau)
+        log(f"[oracle] {name}, threads {threads or 'all'}")
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            ogw.sigma_evaluation(V, G, g, wl.mesh, wl.ns)
+            dt = time.perf_counter() - t0
+        out["runs"].append({"workload": name, "threads": threads or out["host"]["logical_cpus"],
+                            "seconds_per_eval": dt,
+                            "gflops": contraction_flops(wl.nk, wl.nao, wl.naux, wl.ntau) / dt / 1e9})
+        log(f"[oracle] {name}: {dt:.2f} s per evaluation")
+    return out
+
+
 def cpu_baseline(wl, ntau_sample):
     """The CPU oracle, as it stands, timed on this host on a bounded sample of
     the same workload: one q-point, `ntau_sample` tau nodes of the
@@ -90,7 +139,7 @@ def cpu_baseline(wl, ntau_sample):
             "sample": (f"one q-point and {ntau_sample} of {wl.ntau} tau nodes of the polarization "
                        f"and self-energy contractions at the full {wl.name} shape "
                        f"({t1 - t0:.2f} s + {t2 - t1:.2f} s), scaled by Nk*ntau/{ntau_sample}"),
-            "seconds_per_eval_extrapolated": t_eval}
+            "seconds_per_eval_extrapolated": t_eval, "host": host_info()}
 
 
 def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
@@ -281,6 +330,9 @@ def main():
                     help="instead of the step benchmark: plain fp64 damped loop vs DIIS in fp64 "
                          "and in mixed precision to --tol-mixed (default workload si-4x4x4)")
     ap.add_argument("--tol-mixed", type=float, default=1e-6)
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="instead of the step benchmark: time whole oracle evaluations on the CPU "
+                         "(tiny-2x2x2 all threads and one thread, ad-3x3x3 all threads)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -288,6 +340,10 @@ def main():
               "the path shards over q across GPUs by design but no multi-GPU run is built.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_timings:
+        print(json.dumps(oracle_timings()), flush=True)
+        return
 
     import numpy as np
     import torch
