@@ -189,6 +189,64 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
     return res
 
 
+def ir_comparison(path, V, H0, S, wl, lam, eps, ms_step_cheb):
+    """The same workload on intermediate-representation grids (Sec. IV.C;
+    ntau = the IR basis size for lambda, eps): one Sigma+Pi evaluation from G0
+    on each grid, one damped scGW step on the IR grids, and how far the two
+    representations' Sigma lie apart (Sigma_inf, and Sigma~(i w_n) at the
+    Matsubara frequencies both sparse sets hold)."""
+    import numpy as np
+    import torch
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.scgw import GWPath
+    ctx_ir = gw.Context(wl.mesh, wl.nao, wl.naux, None, wl.beta, ns=wl.ns, ir=(lam, eps))
+    p_ir = GWPath(ctx_ir, V, H0, S, wl.n_target)
+    st_c, st_i = path.start(0.0), p_ir.start(0.0)
+    # the same G0 on both grids: Dyson at the chemical potential of the
+    # Chebyshev search (in a gap the roots of the two counts differ)
+    gw.gw_dyson_G(ctx_ir, H0, S, None, None, st_c.mu, st_i.G_iw)
+    gw.gw_iw_to_tau(ctx_ir, gw.GW_FERMION, st_i.G_iw, st_i.G_tau)
+    p_ir.sigma(st_i.G_tau)                             # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    si_c, ss_c = path.sigma(st_c.G_tau)
+    torch.cuda.synchronize()
+    t_c = time.perf_counter() - t0
+    si_c, ss_c = si_c.cpu().numpy(), ss_c.cpu().numpy()
+    t0 = time.perf_counter()
+    si_i, ss_i = p_ir.sigma(st_i.G_tau)
+    torch.cuda.synchronize()
+    t_i = time.perf_counter() - t0
+    si_i, ss_i = si_i.cpu().numpy(), ss_i.cpu().numpy()
+    gc, gi = path.ctx.get_grids(), ctx_ir.get_grids()
+    wc = dict(zip(gc["nF"].tolist(), np.tensordot(gc["TF"], ss_c, axes=(1, 0))))
+    wi = dict(zip(gi["nF"].tolist(), np.tensordot(gi["TF"], ss_i, axes=(1, 0))))
+    common = sorted(set(wc) & set(wi))
+    d_iw = max(float(np.abs(wc[n] - wi[n]).max()) for n in common) if common else None
+    steps = 2
+    p_ir.step(st_i)                                    # warm-up step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p_ir.step(st_i)
+    torch.cuda.synchronize()
+    ms_ir = 1e3 * (time.perf_counter() - t0) / steps
+    res = {"lambda": lam, "eps": eps, "ntau": ctx_ir.ntau, "nw_f": ctx_ir.nw_f, "nw_b": ctx_ir.nw_b,
+           "ntau_chebyshev": path.ctx.ntau,
+           "sigma_eval_s_chebyshev": t_c, "sigma_eval_s_ir": t_i, "evals_per_s_ir": 1.0 / t_i,
+           "speedup_eval": t_c / t_i, "ms_per_step_ir": ms_ir, "speedup_step": ms_step_cheb / ms_ir,
+           "max_abs_dSigma_inf_Ha": float(np.abs(si_c - si_i).max()),
+           "max_abs_dSigma_iw_common_Ha": d_iw, "common_frequencies": len(common),
+           "note": "G0 of H0 at the same mu on each grid; Sigma~(i w) compared where the sparse sets "
+                   "share Matsubara indices; the IR step then runs its own mu search"}
+    ctx_ir.close()
+    del p_ir
+    torch.cuda.empty_cache()
+    log(f"[bench] IR grids (ntau {res['ntau']}): {t_i:.2f} s vs Chebyshev ({path.ctx.ntau}) {t_c:.2f} s per "
+        f"evaluation, step {ms_ir:.0f} ms; max|dSigma| {res['max_abs_dSigma_inf_Ha']:.1e} / {d_iw}")
+    return res
+
+
 def compare_solvers(path, wl, tol):
     """Damped fixed point, Pulay DIIS and Newton-Krylov (GMRES(20)) to
     max |Sigma[G(x)] - x| < tol, all on the fp64 path; the fixed point and
@@ -322,6 +380,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision (fp32 MFMA) comparison")
+    ap.add_argument("--no-ir", action="store_true",
+                    help="skip the comparison with intermediate-representation grids")
+    ap.add_argument("--ir-wmax", type=float, default=5.0,
+                    help="omega_max (Ha) of the IR grids: lambda = beta omega_max")
+    ap.add_argument("--ir-eps", type=float, default=1e-12)
     ap.add_argument("--compare-solvers", action="store_true",
                     help="instead of the step benchmark: damped fixed point vs DIIS vs Newton-Krylov "
                          "to the same residual (default workload ad-3x3x3)")
@@ -449,6 +512,8 @@ def main():
     }
     if not args.no_mixed:
         out["mixed_fp32"] = mixed_comparison(ctx, path, st, V, H0, S, wl)
+    if not args.no_ir:
+        out["ir_grids"] = ir_comparison(path, V, H0, S, wl, wl.beta * args.ir_wmax, args.ir_eps, ms_step)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_tau)

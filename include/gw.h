@@ -144,6 +144,36 @@ gw_status gw_set_grids(gw_ctx* ctx, const double* tau, const long long* nF, cons
                        const gw_z* TF, const gw_z* TFp, const gw_z* TB, const gw_z* TBp,
                        const double* w);
 
+/* Intermediate-representation (IR) grids with sparse sampling on both axes
+ * (Sec. IV.C: dynamical quantities expanded in the IR basis, its cutoff
+ * lambda chosen above beta times the bandwidth, sampled sparsely in tau and
+ * in Matsubara frequency).  Host-only arithmetic:
+ *   basis: the singular-value expansion of the logistic kernel
+ *     K(x, y) = exp(-lambda y (x + 1) / 2) / (1 + exp(-lambda y)) on
+ *     x = 2 tau / beta - 1, y = omega / omega_max, lambda = beta omega_max
+ *     (one basis for fermionic and bosonic functions), by an SVD on composite
+ *     Gauss-Legendre rules; L = the number of singular values above eps times
+ *     the largest, rounded up to even; basis functions by the Nystrom
+ *     extension, whose Matsubara transforms are closed forms;
+ *   tau nodes: the L roots of the first basis function left out (mirrored:
+ *     tau_{L-1-i} = beta - tau_i);
+ *   Matsubara sets: symmetric pairs chosen greedily by the largest residual
+ *     of their (column-scaled) transform rows among |n| < 4 lambda / pi + 4 L:
+ *     L fermionic, L + 1 bosonic;
+ *   tables: T = Uhat U(tau)^{-1}, Tp = U(tau) Uhat^+, density row
+ *     w = u(beta) U(tau)^{-1}.
+ * gw_ir_size returns L for (lambda, eps) (lambda in 1..1e5, eps in
+ * 1e-14..1e-2; otherwise GW_ERR_ARG); a context for IR grids is created with
+ * ntau = L, nw_f = L, nw_b = L + 1.  gw_ir_grids_host fills HOST arrays of
+ * the sizes of gw_get_grids (each may be NULL) without a context;
+ * gw_build_ir_grids installs the tables in a context whose dims match
+ * (GW_ERR_ARG otherwise) and synchronises once for the uploads.  The
+ * expansion is cached per (lambda, eps) for the life of the process.        */
+gw_status gw_ir_size(double lambda, double eps, int* ntau);
+gw_status gw_ir_grids_host(double beta, double lambda, double eps, int ntau, double* tau, long long* nF,
+                           long long* nB, gw_z* TF, gw_z* TFp, gw_z* TB, gw_z* TBp, double* w);
+gw_status gw_build_ir_grids(gw_ctx* ctx, double lambda, double eps);
+
 /* Copy the host tables out (each pointer is a HOST array and may be NULL):
  * tau[ntau], nF[nw_f], nB[nw_b], TF[nw_f*ntau], TFp[ntau*nw_f],
  * TB[nw_b*ntau], TBp[ntau*nw_b] (row-major), w[ntau].                       */

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgw.so")
-SOURCES = ["gw_kernels.hip", "gw_api.hip", "grids.cpp"]
+SOURCES = ["gw_kernels.hip", "gw_api.hip", "grids.cpp", "ir.cpp"]
 
 
 def source_hash():

@@ -15,6 +15,7 @@
 #include "../../include/gw.h"
 #include "grids.h"
 #include "gw_kernels.h"
+#include "ir.h"
 
 // Fixed scratch for gw_polarization_noalloc: a file-scope device array, one
 // copy per GPU for the life of the process.  Host code never passes the
@@ -503,6 +504,73 @@ gw_status gw_set_grids(gw_ctx* c, const double* tau, const long long* nF, const 
   } catch (const std::exception& e) {
     return fail(c, GW_ERR_ARG, e.what());
   }
+  return install_grids(c, g);
+}
+
+// ------------------------------------------------ IR grids (Sec. IV.C) ---
+static gw_status check_ir(double lambda, double eps) {
+  if (!(lambda >= 1.0 && lambda <= 1e5) || !(eps >= 1e-14 && eps <= 1e-2)) return GW_ERR_ARG;
+  return GW_OK;
+}
+
+gw_status gw_ir_size(double lambda, double eps, int* ntau) {
+  if (!ntau || check_ir(lambda, eps) != GW_OK) return GW_ERR_ARG;
+  try {
+    *ntau = gwir::ir_size(lambda, eps);
+  } catch (const std::exception&) {
+    return GW_ERR_ARG;
+  }
+  return GW_OK;
+}
+
+static gw_status make_ir(double beta, double lambda, double eps, int ntau, HostGrids& g, std::string& why) {
+  if (!(beta > 0.0) || !std::isfinite(beta) || check_ir(lambda, eps) != GW_OK) {
+    why = "beta must be positive, lambda in 1..1e5 and eps in 1e-14..1e-2";
+    return GW_ERR_ARG;
+  }
+  try {
+    gwir::IRTables t;
+    if (gwir::ir_size(lambda, eps) != ntau) {
+      why = "ntau differs from the IR basis size (gw_ir_size)";
+      return GW_ERR_ARG;
+    }
+    gwir::ir_grids(beta, lambda, eps, t);
+    g.tau = t.tau; g.x = t.x; g.w = t.w; g.nF = t.nF; g.nB = t.nB;
+    g.TF = t.TF; g.TFp = t.TFp; g.TB = t.TB; g.TBp = t.TBp;
+    finish_grids(beta, g);
+  } catch (const std::exception& e) {
+    why = e.what();
+    return GW_ERR_ARG;
+  }
+  return GW_OK;
+}
+
+gw_status gw_ir_grids_host(double beta, double lambda, double eps, int ntau, double* tau, long long* nF,
+                           long long* nB, gw_z* TF, gw_z* TFp, gw_z* TB, gw_z* TBp, double* w) {
+  HostGrids g;
+  std::string why;
+  gw_status s = make_ir(beta, lambda, eps, ntau, g, why);
+  if (s != GW_OK) return s;
+  if (tau) std::memcpy(tau, g.tau.data(), g.tau.size() * 8);
+  if (nF) std::memcpy(nF, g.nF.data(), g.nF.size() * 8);
+  if (nB) std::memcpy(nB, g.nB.data(), g.nB.size() * 8);
+  if (TF) std::memcpy(TF, g.TF.data(), g.TF.size() * 16);
+  if (TFp) std::memcpy(TFp, g.TFp.data(), g.TFp.size() * 16);
+  if (TB) std::memcpy(TB, g.TB.data(), g.TB.size() * 16);
+  if (TBp) std::memcpy(TBp, g.TBp.data(), g.TBp.size() * 16);
+  if (w) std::memcpy(w, g.w.data(), g.w.size() * 8);
+  return GW_OK;
+}
+
+gw_status gw_build_ir_grids(gw_ctx* c, double lambda, double eps) {
+  if (!c) return GW_ERR_ARG;
+  const int nt = c->d.ntau;
+  if (c->d.nw_f != nt || c->d.nw_b != nt + 1)
+    return fail(c, GW_ERR_ARG, "IR grids need nw_f = ntau and nw_b = ntau + 1");
+  HostGrids g;
+  std::string why;
+  gw_status s = make_ir(c->d.beta, lambda, eps, nt, g, why);
+  if (s != GW_OK) return fail(c, s, why);
   return install_grids(c, g);
 }
 

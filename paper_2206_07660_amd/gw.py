@@ -31,7 +31,8 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_polarization_vjp", "gw_hf_vjp", "gw_dyson_jvp", "gw_axpby", "gw_dot",
            "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
            "gw_hermitize", "gw_set_mu_window", "gw_finite_size", "gw_screened_W_phi",
-           "gw_set_grids", "gw_sigma", "gw_sigma_jvp", "gw_sigma_vjp", "gw_polarization_noalloc"]
+           "gw_set_grids", "gw_sigma", "gw_sigma_jvp", "gw_sigma_vjp", "gw_polarization_noalloc",
+           "gw_ir_size", "gw_ir_grids_host", "gw_build_ir_grids"]
 
 
 class GwError(RuntimeError):
@@ -98,6 +99,9 @@ def load():
         "gw_dot": ([P, LL, P, P, P], I),
         "gw_profile_read": ([P, I, P, P, P], I),
         "gw_grids_host": ([D, I, P, P, P, P, P, P, P, P, P, P], I),
+        "gw_ir_size": ([D, D, P], I),
+        "gw_ir_grids_host": ([D, D, D, I, P, P, P, P, P, P, P, P], I),
+        "gw_build_ir_grids": ([P, D, D], I),
         "gw_status_string": ([I], ctypes.c_char_p),
         "gw_last_error": ([P], ctypes.c_char_p),
     }
@@ -145,16 +149,47 @@ def gw_grids_host(beta, ntau, nF=None, nB=None):
     return out
 
 
+def gw_ir_size(lam, eps):
+    """Basis size L of the IR grids for (lambda, eps) (host only)."""
+    L = load()
+    n = ctypes.c_int()
+    st = L.gw_ir_size(float(lam), float(eps), ctypes.byref(n))
+    if st != GW_OK:
+        raise GwError(st, "gw_ir_size: " + L.gw_status_string(st).decode())
+    return n.value
+
+
+def gw_ir_grids_host(beta, lam, eps):
+    """IR grid tables (host only): dict with tau, nF, nB, TF, TFp, TB, TBp, w."""
+    L = load()
+    nt = gw_ir_size(lam, eps)
+    nf, nb = nt, nt + 1
+    out = dict(tau=np.zeros(nt), nF=np.zeros(nf, np.int64), nB=np.zeros(nb, np.int64),
+               TF=np.zeros((nf, nt), np.complex128), TFp=np.zeros((nt, nf), np.complex128),
+               TB=np.zeros((nb, nt), np.complex128), TBp=np.zeros((nt, nb), np.complex128),
+               w=np.zeros(nt))
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    st = L.gw_ir_grids_host(float(beta), float(lam), float(eps), nt, p(out["tau"]), p(out["nF"]),
+                            p(out["nB"]), p(out["TF"]), p(out["TFp"]), p(out["TB"]), p(out["TBp"]),
+                            p(out["w"]))
+    if st != GW_OK:
+        raise GwError(st, "gw_ir_grids_host: " + L.gw_status_string(st).decode())
+    return out
+
+
 class Context:
     """One library context: dimensions, grids, stream and workspace."""
 
     def __init__(self, mesh, nao, naux, ntau, beta, ns=2, nF=None, nB=None, tau_chunk=None,
-                 max_nq=None, stream=None, workspace_gb=None, precision="fp64", grids=None):
+                 max_nq=None, stream=None, workspace_gb=None, precision="fp64", grids=None, ir=None):
         """grids: None builds the Chebyshev tables in the library
         (gw_build_grids with the Matsubara sets nF, nB or its own greedy
         choice); or a dict with tau, nF, nB, TF, TFp, TB, TBp, w (numpy host
         arrays, e.g. an intermediate-representation basis) installed with
-        gw_set_grids, whose shapes fix nw_f and nw_b."""
+        gw_set_grids, whose shapes fix nw_f and nw_b.
+        ir: None, or (lambda, eps): intermediate-representation grids built by
+        the library (gw_build_ir_grids); ntau is then the basis size
+        (pass None) with nw_f = ntau and nw_b = ntau + 1."""
         import torch
         L = load()
         if precision not in ("fp64", "fp32"):
@@ -163,7 +198,13 @@ class Context:
         self.v_dtype = torch.complex128 if precision == "fp64" else torch.complex64
         self.mesh = tuple(int(m) for m in mesh)
         self.nk = int(np.prod(self.mesh))
-        self.nao, self.naux, self.ntau, self.beta, self.ns = int(nao), int(naux), int(ntau), float(beta), int(ns)
+        self.nao, self.naux, self.beta, self.ns = int(nao), int(naux), float(beta), int(ns)
+        self.ntau = None if ntau is None else int(ntau)
+        if ir is not None:
+            n_ir = gw_ir_size(*ir)
+            if ntau is not None and int(ntau) != n_ir:
+                raise ValueError(f"ntau {ntau} differs from the IR basis size {n_ir}")
+            self.ntau = n_ir
         if grids is None:
             self.nw_f, self.nw_b = self.ntau, self.ntau + 1
         else:
@@ -177,7 +218,9 @@ class Context:
         if st != GW_OK:
             raise GwError(st, "gw_create failed: " + L.gw_status_string(st).decode())
         self.h = h
-        if grids is None:
+        if ir is not None:
+            self._check(L.gw_build_ir_grids(self.h, float(ir[0]), float(ir[1])), "gw_build_ir_grids")
+        elif grids is None:
             nf = None if nF is None else (ctypes.c_longlong * self.nw_f)(*[int(x) for x in nF])
             nb = None if nB is None else (ctypes.c_longlong * self.nw_b)(*[int(x) for x in nB])
             self._check(L.gw_build_grids(self.h, nf, nb), "gw_build_grids")

@@ -82,3 +82,49 @@ def test_host_grids_given_sets_are_used():
     p = gw.gw_grids_host(20.0, 20, nF=o.nF, nB=o.nB)
     assert np.array_equal(p["nF"], o.nF)
     assert np.abs(p["TF"] - o.TF).max() < 1e-11
+
+
+# ------------------------------------------------------- IR grids (host) ---
+@pytest.mark.parametrize("beta,lam,eps", [(100.0, 500.0, 1e-10), (100.0, 500.0, 1e-12),
+                                          (200.0, 1000.0, 1e-12), (50.0, 200.0, 1e-10)])
+def test_ir_host_grids(beta, lam, eps):
+    """The library's IR tables: the oracle's basis size and Matsubara sets, tau
+    nodes within the rounding of the small singular vectors (1e-5 beta), and
+    transforms that are exact for single poles to the cutoff eps (checked
+    against closed forms, not against the oracle's tables)."""
+    from oracle import ir
+    L = gw.gw_ir_size(lam, eps)
+    g = gw.gw_ir_grids_host(beta, lam, eps)
+    o = ir.IRGrids(beta, lam, eps)
+    assert L == o.ntau and len(g["tau"]) == L
+    assert np.array_equal(g["nF"], o.nF) and np.array_equal(g["nB"], o.nB)
+    assert np.abs(g["tau"] - o.tau).max() < 1e-5 * beta
+    tau = g["tau"]
+    assert np.abs(tau + tau[::-1] - beta).max() < 1e-12 * beta
+    wF, wB = (2 * g["nF"] + 1) * np.pi / beta, 2 * g["nB"] * np.pi / beta
+    wmax = lam / beta
+    ef = eff = eb = ew = 0.0
+    for xi in np.linspace(-0.95 * wmax, 0.95 * wmax, 41):
+        G = -np.exp(np.where(xi >= 0, -xi * tau, xi * (beta - tau))) / (1.0 + np.exp(-beta * abs(xi)))
+        ex = 1.0 / (1j * wF - xi)
+        ef = max(ef, np.abs(g["TF"] @ G - ex).max())
+        eff = max(eff, np.abs(g["TFp"] @ ex - G).max())
+        ew = max(ew, abs(g["w"] @ G + 1.0 / (1.0 + np.exp(beta * xi))))       # G(beta^-) = -f
+        if abs(xi) > 1e-12:
+            B = (-np.exp(-xi * tau) / -np.expm1(-beta * xi)) if xi > 0 else \
+                (np.exp(xi * (beta - tau)) / -np.expm1(beta * xi))
+            exb = 1.0 / (1j * wB - xi)
+            eb = max(eb, np.abs(g["TB"] @ B - exb).max() / np.abs(exb).max())
+    assert ef < 20 * eps and eb < 20 * eps and eff < 200 * eps and ew < 20 * eps
+
+
+def test_ir_host_grids_reject_bad_input():
+    for lam, eps in ((0.5, 1e-10), (1e6, 1e-10), (100.0, 0.0), (100.0, 0.5)):
+        with pytest.raises(gw.GwError):
+            gw.gw_ir_size(lam, eps)
+    L = gw.load()
+    n = gw.gw_ir_size(100.0, 1e-10)
+    z = np.zeros(4 * n * n, np.complex128)
+    p = z.ctypes.data_as(ctypes.c_void_p)
+    assert L.gw_ir_grids_host(10.0, 100.0, 1e-10, n + 2, None, None, None, p, None, None, None, None) \
+        == gw.GW_ERR_ARG

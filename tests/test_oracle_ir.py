@@ -145,3 +145,33 @@ def test_size_grows_with_cutoff_and_precision():
     assert L[(100.0, 1e-8)] < L[(100.0, 1e-12)]
     s = ir.Basis(1000.0, 1e-12).s
     assert np.all(np.diff(s[:80]) < 0)
+
+
+def test_sigma_chain_same_on_ir_and_chebyshev_grids():
+    """The whole Sigma chain from the same G0 on IR grids and on a Chebyshev
+    grid fine enough to be exact here: Sigma_inf and Sigma~(i w_n) at the
+    lowest Matsubara frequencies agree (each grid evaluates its own tau
+    representation at those frequencies)."""
+    from oracle import grids as og
+    from paper_2206_07660_amd import inputs as inp
+    wl = inp.small_workload(mesh=(2, 1, 1), nao=3, naux=6, ntau=40, beta=10.0, seed=17)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    mu = 0.1
+    cheb = og.Grids(wl.beta, 40)
+    irg = ir.IRGrids(wl.beta, 60.0, 1e-12)
+    out = {}
+    nn = np.arange(-4, 4)
+    nu = (2 * nn + 1) * np.pi / wl.beta
+    for name, g in (("cheb", cheb), ("ir", irg)):
+        G = gw.g0_tau(H0, S, mu, wl.beta, g.tau)
+        sinf, stau, _ = gw.sigma_evaluation(V, G, g, wl.mesh, wl.ns)
+        if name == "cheb":
+            T = og.transform_matrix(nu, wl.beta, 40)
+        else:
+            T = g.basis.uhat(nu, wl.beta, "F") @ np.linalg.inv(g.basis.u(g.x))
+        out[name] = (sinf, np.tensordot(T, stau, axes=(1, 0)))
+    d_inf = np.abs(out["cheb"][0] - out["ir"][0]).max()
+    d_iw = np.abs(out["cheb"][1] - out["ir"][1]).max()
+    print(f"IR ({irg.ntau} nodes) vs Chebyshev (40): Sigma_inf {d_inf:.1e}, Sigma~(i w) {d_iw:.1e} "
+          f"(|Sigma~(i w)| {np.abs(out['cheb'][1]).max():.3f})")
+    assert d_inf < 1e-10 and d_iw < 1e-9
