@@ -293,13 +293,18 @@ def sigma_evaluation(V, G_tau, grids, mesh, ns):
 # ---------------------------------------------- damped scGW (Sec. IV.A) ------
 def scgw(H0, S, V, grids, mesh, ns, n_target, n_iter, alpha=0.5, mu0=0.0):
     """Damped fixed-point scGW (reading R10).  Returns the history of
-    (mu, Sigma_inf, Sigma~(tau), G(tau)) after each iteration, index 0 = start."""
+    (mu, Sigma_inf, Sigma~(tau), G(tau)) after each iteration, index 0 = start.
+    n_target None keeps mu = mu0 fixed (no search; the grand-canonical
+    iteration that thermodynamic derivatives at fixed mu need)."""
     nk, n, _ = H0.shape
     ntau = grids.ntau
     sig_inf = np.zeros((nk, n, n), np.complex128)
     sig_tau = np.zeros((ntau, nk, n, n), np.complex128)
     sig_iw = to_iw(grids.TF, sig_tau)
-    mu, G_iw, _ = find_mu(H0, S, sig_inf, sig_iw, n_target, grids, ns, mu0)
+    if n_target is None:
+        mu, G_iw = mu0, dyson(H0, S, sig_inf, sig_iw, mu0, grids.wF)
+    else:
+        mu, G_iw, _ = find_mu(H0, S, sig_inf, sig_iw, n_target, grids, ns, mu0)
     G_tau = to_tau(grids.TFp, G_iw)
     hist = [(mu, sig_inf.copy(), sig_tau.copy(), G_tau.copy())]
     for _ in range(n_iter):
@@ -307,7 +312,10 @@ def scgw(H0, S, V, grids, mesh, ns, n_target, n_iter, alpha=0.5, mu0=0.0):
         sig_inf = (1.0 - alpha) * sig_inf + alpha * s_inf
         sig_tau = (1.0 - alpha) * sig_tau + alpha * s_tau
         sig_iw = to_iw(grids.TF, sig_tau)
-        mu, G_iw, _ = find_mu(H0, S, sig_inf, sig_iw, n_target, grids, ns, mu)
+        if n_target is None:
+            G_iw = dyson(H0, S, sig_inf, sig_iw, mu, grids.wF)
+        else:
+            mu, G_iw, _ = find_mu(H0, S, sig_inf, sig_iw, n_target, grids, ns, mu)
         G_tau = to_tau(grids.TFp, G_iw)
         hist.append((mu, sig_inf.copy(), sig_tau.copy(), G_tau.copy()))
     return hist
