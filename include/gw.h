@@ -197,7 +197,7 @@ gw_status gw_grids_host(double beta, int ntau, const long long* nF, const long l
  * (caller-owned, >= 256-byte aligned) and the tau chunk to use; calls that
  * need more than that buffer return GW_ERR_WORKSPACE.                       */
 enum { GW_OP_POLARIZATION = 0, GW_OP_SELF_ENERGY = 1, GW_OP_SCREENED_W = 2, GW_OP_HF = 3,
-       GW_OP_DYSON_JVP = 4, GW_OP_SIGMA = 5 };
+       GW_OP_DYSON_JVP = 4, GW_OP_SIGMA = 5, GW_OP_THERMO = 6 };
 size_t gw_workspace_bytes(const gw_ctx* ctx, int op, int tau_chunk);
 gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
 
@@ -361,6 +361,32 @@ gw_status gw_finite_size(gw_ctx* ctx, const gw_z* S, double chi, const gw_z* gam
  * the call synchronise.  Errors as the calls it is made of.                 */
 gw_status gw_sigma(gw_ctx* ctx, const void* V, const gw_z* G_tau, gw_z* gamma, gw_z* Sig_inf,
                    gw_z* Sig_tau, gw_z* P_tau, gw_z* P0_iw, gw_z* Pt_iw, double* phi);
+
+/* Grand potential and energies of Sec. III.C (per unit cell, Ha), from the
+ * self-energy (Sig_inf [k][i][j], Sig_iw [n][k][i][j] on the fermionic
+ * sparse set; either may be NULL for zero) at chemical potential mu, with G
+ * from the Dyson equation and Phi~ given (gw_screened_W_phi or gw_sigma):
+ *   Omega = Phi_inf + Phi~ - Tr ln(-G^{-1}) - Tr{Sigma G}          (Eq. GP)
+ *   Phi_inf = (1/2) Tr{Sigma_inf gamma}                             (Eq. Phi_GW)
+ *   Tr ln(-G^{-1}) = (ns/Nk) sum_k [ (1/beta) sum_a ln(1 + e^{-beta xi_a})
+ *                    + (1/beta) sum_n ln|det(I - G_ref Sigma~(i w_n))| ]
+ *     with xi_a the eigenvalues of (H0 + Sig_inf - mu S, S) and G_ref the
+ *     Green's function of the static part;
+ *   Tr{Sigma G} = (ns/Nk) sum_k [ tr(Sig_inf gamma) + (1/beta) sum_n tr(Sig~ G) ];
+ *   E_GM = Tr{H0 gamma} + (1/2) Tr{Sigma G} (Galitskii-Migdal).
+ * Every equal-time trace takes G(0^-) = gamma = -G(beta^-).  The Matsubara
+ * sums of the decaying terms are read off the sparse grid as the symmetric
+ * average of the fitted tau function at 0+ and 0-: (1/beta) sum_n F(i w_n)
+ * = -sum_n Re(r_n) Re F(i w_n), r = w TFp, so only ln|det| enters.  n_e is
+ * the electron count of G.  Uses the GW_OP_THERMO workspace; copies H0,
+ * S and Sig_inf to the host for the Nk small eigenvalue problems;
+ * synchronises.  GW_ERR_SINGULAR for a zero pivot in either Dyson solve,
+ * GW_ERR_ARG for an S that is not positive definite.                       */
+typedef struct {
+  double omega, phi_inf, phi_tilde, tr_ln, tr_sigma_g, e_one_body, e_gm, n_e;
+} gw_thermo;
+gw_status gw_thermodynamics(gw_ctx* ctx, const gw_z* H0, const gw_z* S, const gw_z* Sig_inf,
+                            const gw_z* Sig_iw, double mu, double phi_tilde, gw_thermo* out);
 
 /* Damped update and convergence measure of the scGW loop (Sec. IV.A):
  * Y <- (1 - alpha) Y + alpha X_new over n complex elements.  X_new may be

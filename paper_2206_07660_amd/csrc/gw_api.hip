@@ -639,6 +639,11 @@ size_t gw_workspace_bytes(const gw_ctx* c, int op, int tau_chunk) {
     case GW_OP_SIGMA:
       if (tau_chunk < 1 || tau_chunk > c->d.ntau) return 0;
       return sigma_front_bytes(c, tau_chunk) + perq_bytes(c);
+    case GW_OP_THERMO: {
+      const size_t nb = (size_t)c->d.nw_f * c->nk;
+      return align256(nb * c->n2 * 16) + 3 * align256(nb * 8) + align256((size_t)c->nk * c->n2 * 16) +
+             align256((size_t)c->d.nw_f * 16) + align256((size_t)c->nk * 3 * 8);
+    }
   }
   return 0;
 }
@@ -1878,6 +1883,188 @@ gw_status gw_sigma_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt_t
     if ((s = gw_polarization_vjp(c, V, G, p.tb, q, 1, G_bar)) != GW_OK) return s;
   }
   return gw_hf_vjp(c, V, Sinf_bar, G_bar);
+}
+
+// ------------------------------------------- thermodynamics (Sec. III.C) ---
+// Eigenvalues of the Hermitian pencil (H, S), S positive definite: Cholesky
+// S = L L^H, A = L^{-1} H L^{-H}, cyclic complex Jacobi rotations on A.
+static bool pencil_eigenvalues(const gwgrid::cd* H, const gwgrid::cd* S, int n, double* ev) {
+  using cd = gwgrid::cd;
+  std::vector<cd> L((size_t)n * n, 0.0), A((size_t)n * n), X((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    double d = S[(size_t)j * n + j].real();
+    for (int p = 0; p < j; ++p) d -= std::norm(L[(size_t)j * n + p]);
+    if (!(d > 0.0)) return false;
+    L[(size_t)j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      cd v = S[(size_t)i * n + j];
+      for (int p = 0; p < j; ++p) v -= L[(size_t)i * n + p] * std::conj(L[(size_t)j * n + p]);
+      L[(size_t)i * n + j] = v / L[(size_t)j * n + j];
+    }
+  }
+  // X = L^{-1} M for a square M (forward substitution per column)
+  auto lsolve = [&](const std::vector<cd>& M, std::vector<cd>& out) {
+    for (int c = 0; c < n; ++c)
+      for (int i = 0; i < n; ++i) {
+        cd v = M[(size_t)i * n + c];
+        for (int p = 0; p < i; ++p) v -= L[(size_t)i * n + p] * out[(size_t)p * n + c];
+        out[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+      }
+  };
+  std::vector<cd> Hm(H, H + (size_t)n * n), Y((size_t)n * n);
+  lsolve(Hm, X);                                       // X = L^{-1} H
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Y[(size_t)i * n + j] = std::conj(X[(size_t)j * n + i]);
+  lsolve(Y, A);                                        // A = L^{-1} X^H = (X L^{-H})^H
+  for (int i = 0; i < n; ++i)                          // A is Hermitian: make it exactly so
+    for (int j = i; j < n; ++j) {
+      const cd v = 0.5 * (A[(size_t)i * n + j] + std::conj(A[(size_t)j * n + i]));
+      A[(size_t)i * n + j] = v;
+      A[(size_t)j * n + i] = std::conj(v);
+    }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += std::norm(A[(size_t)i * n + j]);
+        if (i != j) off += std::norm(A[(size_t)i * n + j]);
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const cd b = A[(size_t)p * n + q];
+        const double ab = std::abs(b);
+        if (ab == 0.0) continue;
+        const cd ph = b / ab;                           // e^{i phi}
+        const double a = A[(size_t)p * n + p].real(), d = A[(size_t)q * n + q].real();
+        const double tau = (d - a) / (2.0 * ab);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < n; ++k) {                   // A <- A U
+          const cd x = A[(size_t)k * n + p], y = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = c * x - sn * std::conj(ph) * y;
+          A[(size_t)k * n + q] = sn * x + c * std::conj(ph) * y;
+        }
+        for (int k = 0; k < n; ++k) {                   // A <- U^H A
+          const cd x = A[(size_t)p * n + k], y = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = c * x - sn * ph * y;
+          A[(size_t)q * n + k] = sn * x + c * ph * y;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) ev[i] = A[(size_t)i * n + i].real();
+  return true;
+}
+
+gw_status gw_thermodynamics(gw_ctx* c, const gw_z* H0, const gw_z* S, const gw_z* Sinf, const gw_z* Siw,
+                            double mu, double phi_tilde, gw_thermo* out) {
+  gw_status s = need_grids(c);
+  if (s != GW_OK) return s;
+  if (!H0 || !S || !out) return fail(c, GW_ERR_ARG, "NULL array");
+  if (!std::isfinite(mu) || !std::isfinite(phi_tilde)) return fail(c, GW_ERR_ARG, "mu or phi_tilde is not finite");
+  if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_THERMO, 1))
+    return fail(c, GW_ERR_WORKSPACE, "thermodynamics workspace too small (GW_OP_THERMO)");
+  const int nk = c->nk, nao = c->d.nao, nw = c->d.nw_f, ns = c->d.ns;
+  const long long n2 = c->n2, nb = (long long)nw * nk;
+  char* p = (char*)c->ws;
+  double2* Giw = (double2*)p;                     // G(i w) [n][k][i][j]
+  p += align256((size_t)nb * n2 * 16);
+  double* ld = (double*)p;                        // ln|det M|
+  p += align256((size_t)nb * 8);
+  double* ldr = (double*)p;                       // ln|det M_ref|
+  p += align256((size_t)nb * 8);
+  double* tr = (double*)p;                        // per-(n, k) weighted traces
+  p += align256((size_t)nb * 8);
+  double2* gam = (double2*)p;                     // gamma [k][i][j]
+  p += align256((size_t)nk * n2 * 16);
+  double2* cw = (double2*)p;                      // (c_n, 0): c_n = -Re r_n
+  p += align256((size_t)nw * 16);
+  double* trk = (double*)p;                       // per-k traces
+  // Dyson at mu with and without Sigma~ (log-determinants), G(i w) kept
+  HIPCHK(c, zero_flag_launch(c->dflag, c->st));
+  DysonArgs a{};
+  a.H0 = (const double2*)H0; a.S = (const double2*)S; a.Sinf = (const double2*)Sinf;
+  a.Siw = (const double2*)Siw; a.wF = c->dwF; a.rrow = c->drrow; a.mu = mu; a.nk = nk; a.nao = nao;
+  a.flag = c->dflag; a.G = Giw; a.logdet = ld;
+  HIPCHK(c, dyson_launch(a, nw, c->st));
+  a.Siw = nullptr; a.G = nullptr; a.logdet = ldr;
+  HIPCHK(c, dyson_launch(a, nw, c->st));
+  if ((s = read_flag(c, "thermodynamics")) != GW_OK) return s;
+  // gamma = -G(beta^-) = -sum_n r_n G(i w_n)
+  GemmDesc g = gemm_desc();
+  g.A = c->drrow; g.B = Giw; g.C = gam;
+  g.M = 1; g.N = nk * (int)n2; g.K = nw;
+  g.am = aff(0); g.ak = aff(1); g.bk = aff((long long)nk * n2); g.bn = aff(1);
+  g.cm = aff(0); g.cn = aff(1);
+  g.alpha_r = -1.0;
+  g.tag = KC_OTHER;
+  if ((s = run(c, g, Ext{0, (long long)nw}, Ext{0, nb * n2}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
+  // Matsubara-sum weights of decaying fermionic functions: c_n = -Re r_n
+  std::vector<double2> cwh(nw);
+  std::vector<double> cnh(nw);
+  for (int n = 0; n < nw; ++n) {
+    cnh[n] = -c->rrow[n].real();
+    cwh[n] = double2{cnh[n], 0.0};
+  }
+  HIPCHK(c, hipMemcpyAsync(cw, cwh.data(), nw * sizeof(double2), hipMemcpyHostToDevice, c->st));
+  if (Siw) HIPCHK(c, wtrace_launch((const double2*)Siw, Giw, cw, nao, nk, nw, tr, c->st, 1));
+  // per-k traces tr[gamma X] for X = S, H0, Sigma_inf
+  std::vector<double> t_s(nk), t_h(nk), t_x(nk, 0.0), t_dyn(nb, 0.0), lm(nb), lr(nb);
+  HIPCHK(c, trace_launch(gam, (const double2*)S, nao, nk, trk, c->st));
+  HIPCHK(c, hipMemcpyAsync(t_s.data(), trk, nk * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, trace_launch(gam, (const double2*)H0, nao, nk, trk + nk, c->st));
+  HIPCHK(c, hipMemcpyAsync(t_h.data(), trk + nk, nk * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  if (Sinf) {
+    HIPCHK(c, trace_launch(gam, (const double2*)Sinf, nao, nk, trk + 2 * nk, c->st));
+    HIPCHK(c, hipMemcpyAsync(t_x.data(), trk + 2 * nk, nk * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  }
+  if (Siw) HIPCHK(c, hipMemcpyAsync(t_dyn.data(), tr, nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(lm.data(), ld, nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(lr.data(), ldr, nb * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  // the static pencil (H0 + Sigma_inf, S) on the host
+  std::vector<gwgrid::cd> hh((size_t)nk * n2), ss((size_t)nk * n2), xx((size_t)nk * n2, 0.0);
+  HIPCHK(c, hipMemcpyAsync(hh.data(), H0, hh.size() * 16, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(ss.data(), S, ss.size() * 16, hipMemcpyDeviceToHost, c->st));
+  if (Sinf) HIPCHK(c, hipMemcpyAsync(xx.data(), Sinf, xx.size() * 16, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const double beta = c->d.beta, pre = (double)ns / nk;
+  double free_sum = 0.0;
+  std::vector<double> ev(nao);
+  for (int k = 0; k < nk; ++k) {
+    std::vector<gwgrid::cd> hk(hh.begin() + (size_t)k * n2, hh.begin() + (size_t)(k + 1) * n2);
+    for (long long e = 0; e < n2; ++e) hk[e] += xx[(size_t)k * n2 + e];
+    if (!pencil_eigenvalues(hk.data(), &ss[(size_t)k * n2], nao, ev.data()))
+      return fail(c, GW_ERR_ARG, "S is not positive definite");
+    for (int i = 0; i < nao; ++i) {
+      const double xi = ev[i] - mu;
+      free_sum += std::max(-xi, 0.0) + std::log1p(std::exp(-beta * std::fabs(xi))) / beta;
+    }
+  }
+  double ln_dyn = 0.0, sg_dyn = 0.0, ne = 0.0, e1 = 0.0, xs = 0.0;
+  for (int n = 0; n < nw; ++n)
+    for (int k = 0; k < nk; ++k) {
+      const size_t i = (size_t)n * nk + k;
+      ln_dyn += cnh[n] * (lm[i] - lr[i]);
+      sg_dyn += t_dyn[i];
+    }
+  for (int k = 0; k < nk; ++k) {
+    ne += t_s[k];
+    e1 += t_h[k];
+    xs += t_x[k];
+  }
+  gw_thermo o{};
+  o.tr_ln = pre * (free_sum + ln_dyn);
+  o.tr_sigma_g = pre * (xs + sg_dyn);
+  o.phi_inf = 0.5 * pre * xs;
+  o.phi_tilde = phi_tilde;
+  o.omega = o.phi_inf + o.phi_tilde - o.tr_ln - o.tr_sigma_g;
+  o.e_one_body = pre * e1;
+  o.e_gm = o.e_one_body + 0.5 * o.tr_sigma_g;
+  o.n_e = pre * ne;
+  if (!std::isfinite(o.omega) || !std::isfinite(o.e_gm))
+    return fail(c, GW_ERR_NONFINITE, "thermodynamics: non-finite result");
+  *out = o;
+  return GW_OK;
 }
 
 }  // extern "C"

@@ -100,6 +100,7 @@ struct DysonArgs {
   double2* G;            // may be null
   double* part;          // may be null
   int* flag;
+  double* logdet;        // may be null: logdet[n*nk+k] = ln|det M| of the Dyson matrix
 };
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st);
@@ -115,8 +116,9 @@ hipError_t axpby_launch(long long n, double ar, double ai, const double2* X, dou
                         double2* Y, hipStream_t st);
 hipError_t dot_launch(long long n, const double2* X, const double2* Y, double* part, int nblk,
                       double* out, hipStream_t st);
+// part[n*nk+k] = Re(r_n tr[P[n][k] S[k]]) (S per k: s_per_w = 0) or with S[n][k] (s_per_w = 1).
 hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, int nao, int nk, int nw,
-                         double* part, hipStream_t st);
+                         double* part, hipStream_t st, int s_per_w = 0);
 // P[b] for b < nmat (n x n, row-major): entries below the diagonal become the
 // conjugates of their mirror images above it.
 hipError_t herm_fill_launch(double2* P, int n, long long nmat, hipStream_t st);

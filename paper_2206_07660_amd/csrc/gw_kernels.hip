@@ -855,6 +855,7 @@ __global__ void __launch_bounds__(256) dyson_k(DysonArgs a) {
   __shared__ int pi_[256];
   __shared__ double2 pinv_s;
   __shared__ int piv_s;
+  double lsum = 0.0;                        // thread 0: sum of ln|pivot|
   const int tid = threadIdx.x, nt = blockDim.x;
   const size_t nn = (size_t)n * n;
   const double w = a.wF[iw];
@@ -913,6 +914,7 @@ __global__ void __launch_bounds__(256) dyson_k(DysonArgs a) {
       const double2 x = M[j * n + j];
       const double den = x.x * x.x + x.y * x.y;
       pinv_s = den > 0.0 ? double2{x.x / den, -x.y / den} : double2{0.0, 0.0};
+      lsum += 0.5 * log(den);
     }
     __syncthreads();
     const double2 q = pinv_s;
@@ -945,6 +947,7 @@ __global__ void __launch_bounds__(256) dyson_k(DysonArgs a) {
       }
     __syncthreads();
   }
+  if (a.logdet && tid == 0) a.logdet[(size_t)iw * a.nk + k] = lsum;
   if (a.G) {
     double2* g = a.G + ((size_t)iw * a.nk + k) * nn;
     for (int e = tid; e < (int)nn; e += nt) g[e] = M[e];
@@ -1192,10 +1195,11 @@ hipError_t dot_launch(long long n, const double2* X, const double2* Y, double* p
 
 // part[n*nk + k] = Re(r_n tr[P[n][k] S[k]])
 __global__ void __launch_bounds__(64) wtrace_k(const double2* P, const double2* S, const double2* r,
-                                               int nao, int nk, double* part) {
+                                               int nao, int nk, double* part, int s_per_w) {
   const int k = blockIdx.x % nk, iw = blockIdx.x / nk;
   const size_t nn = (size_t)nao * nao;
   const double2* p = P + ((size_t)iw * nk + k) * nn;
+  if (s_per_w) S += (size_t)iw * nk * nn;
   double tr = 0.0, ti = 0.0;
   for (int e = threadIdx.x; e < (int)nn; e += 64) {
     const int a = e / nao, b = e % nao;
@@ -1219,8 +1223,8 @@ __global__ void __launch_bounds__(64) wtrace_k(const double2* P, const double2* 
 }
 
 hipError_t wtrace_launch(const double2* P, const double2* S, const double2* r, int nao, int nk, int nw,
-                         double* part, hipStream_t st) {
-  wtrace_k<<<(unsigned)(nw * nk), 64, 0, st>>>(P, S, r, nao, nk, part);
+                         double* part, hipStream_t st, int s_per_w) {
+  wtrace_k<<<(unsigned)(nw * nk), 64, 0, st>>>(P, S, r, nao, nk, part, s_per_w);
   return hipGetLastError();
 }
 

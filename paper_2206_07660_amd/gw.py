@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libgw.so")
  GW_ERR_NONFINITE) = range(8)
 GW_FERMION, GW_BOSON = 0, 1
 GW_PREC_FP64, GW_PREC_FP32 = 0, 1
-GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF, GW_OP_DYSON_JVP, GW_OP_SIGMA = range(6)
+(GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF, GW_OP_DYSON_JVP, GW_OP_SIGMA,
+ GW_OP_THERMO) = range(7)
 KCLASS = dict(other=0, pol_contract=1, pol_producer=2, se_contract=3, se_producer=4,
               se_final=5, transform=6, hf=7, wdyson=8, dyson=9)
 
@@ -32,7 +33,7 @@ EXPORTS = ["gw_create", "gw_destroy", "gw_build_grids", "gw_get_grids", "gw_work
            "gw_synchronize", "gw_status_string", "gw_last_error", "gw_set_hermitian",
            "gw_hermitize", "gw_set_mu_window", "gw_finite_size", "gw_screened_W_phi",
            "gw_set_grids", "gw_sigma", "gw_sigma_jvp", "gw_sigma_vjp", "gw_polarization_noalloc",
-           "gw_ir_size", "gw_ir_grids_host", "gw_build_ir_grids"]
+           "gw_ir_size", "gw_ir_grids_host", "gw_build_ir_grids", "gw_thermodynamics"]
 
 
 class GwError(RuntimeError):
@@ -102,6 +103,7 @@ def load():
         "gw_ir_size": ([D, D, P], I),
         "gw_ir_grids_host": ([D, D, D, I, P, P, P, P, P, P, P, P], I),
         "gw_build_ir_grids": ([P, D, D], I),
+        "gw_thermodynamics": ([P, P, P, P, P, D, D, P], I),
         "gw_status_string": ([I], ctypes.c_char_p),
         "gw_last_error": ([P], ctypes.c_char_p),
     }
@@ -239,7 +241,8 @@ class Context:
                    L.gw_workspace_bytes(self.h, GW_OP_SIGMA, self.tau_chunk),
                    L.gw_workspace_bytes(self.h, GW_OP_SCREENED_W, self.max_nq),
                    L.gw_workspace_bytes(self.h, GW_OP_HF, 1),
-                   L.gw_workspace_bytes(self.h, GW_OP_DYSON_JVP, 1))
+                   L.gw_workspace_bytes(self.h, GW_OP_DYSON_JVP, 1),
+                   L.gw_workspace_bytes(self.h, GW_OP_THERMO, 1))
         self.workspace = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
@@ -499,6 +502,21 @@ def gw_find_mu(ctx, H0, S, Sig_inf, Sig_iw, n_target, mu0=0.0, tol=1e-13, G_iw=N
         _ptr(G_tau, "G_tau", ctx.g_shape()) if G_tau is not None else None,
         ctypes.byref(n)), "gw_find_mu")
     return mu.value, n.value
+
+
+class Thermo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("omega", "phi_inf", "phi_tilde", "tr_ln", "tr_sigma_g",
+                                                "e_one_body", "e_gm", "n_e")]
+
+
+def gw_thermodynamics(ctx, H0, S, Sig_inf, Sig_iw, mu, phi_tilde):
+    """Grand potential (Eq. GP), its parts and the Galitskii-Migdal energy, as a dict."""
+    t = Thermo()
+    ctx._check(load().gw_thermodynamics(
+        ctx.h, _ptr(H0, "H0", ctx.k_shape()), _ptr(S, "S", ctx.k_shape()),
+        _ptr(Sig_inf, "Sig_inf", ctx.k_shape()), _ptr(Sig_iw, "Sig_iw", ctx.giw_shape()),
+        float(mu), float(phi_tilde), ctypes.byref(t)), "gw_thermodynamics")
+    return {n: getattr(t, n) for n, _ in Thermo._fields_}
 
 
 def gw_synchronize(ctx):

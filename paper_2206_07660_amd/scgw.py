@@ -98,3 +98,13 @@ class GWPath:
         st.dsig = max(d1, d2) if want_diff else float("nan")
         st.iteration += 1
         return st
+
+    def thermodynamics(self, st: State, phi=None):
+        """Grand potential (Eq. GP) and Galitskii-Migdal energy of the state's
+        self-energy at its mu (gw_thermodynamics).  phi: Phi~ of the G that
+        produced the self-energy; default: the last sigma() call's (needs
+        want_phi)."""
+        c = self.ctx
+        phi = self.phi if phi is None else float(phi)
+        gw.gw_tau_to_iw(c, gw.GW_FERMION, st.sig_tau, self.sig_iw)
+        return gw.gw_thermodynamics(c, self.H0, self.S, st.sig_inf, self.sig_iw, st.mu, phi)
