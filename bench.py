@@ -247,6 +247,50 @@ def ir_comparison(path, V, H0, S, wl, lam, eps, ms_step_cheb):
     return res
 
 
+def solve(path, wl, args, start=None):
+    """One self-consistent solve to max |Sigma[G(x)] - x| < args.tol from G0
+    with the chosen solver on the given path (precision, grids and mu mode
+    as built); seconds, evaluations, residual history, mu and N_e."""
+    import torch
+    from paper_2206_07660_amd.diis import DIIS
+    from paper_2206_07660_amd.newton import NewtonKrylov
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = begin(path, start)
+    deadline = t0 + args.max_seconds if args.max_seconds else None
+    out = {"solver": args.solve, "mu0": st.mu}
+    if args.solve == "damped":
+        res = []
+        for _ in range(args.max_evals):
+            path.step(st)
+            res.append(st.dsig)
+            log(f"[solve] damped {len(res)}: dSigma {st.dsig:.3e} mu {st.mu:.10f} N_e {st.n_e:.12f}")
+            if st.dsig < args.tol or (deadline and time.perf_counter() > deadline):
+                break
+        out.update(evaluations=len(res), residuals=res, mu=st.mu, n_e=st.n_e)
+    elif args.solve == "diis":
+        dz = DIIS(path, depth=6)
+        x, F = dz.solve(st.sig_inf, st.sig_tau, st.mu, tol=args.tol, max_iter=args.max_evals,
+                        log=lambda m: log(f"[solve] {m}"), deadline=deadline)
+        out.update(evaluations=dz.stats.evaluations, residuals=dz.stats.residuals, mu=dz.mu,
+                   n_e=dz.n_e)
+    else:
+        if start is None:
+            for _ in range(2):
+                path.step(st)
+        nk = NewtonKrylov(path, restart=20, gmres_rtol=1e-3, per_q=args.per_q,
+                          log=lambda m: log(f"[solve] {m}"))
+        x, F = nk.solve(st.sig_inf, st.sig_tau, st.mu, tol=args.tol, max_steps=args.max_evals,
+                        log=lambda m: log(f"[solve] {m}"), deadline=deadline)
+        out.update(evaluations=nk.stats.evaluations + (2 if start is None else 0), jvps=nk.stats.jvps,
+                   newton_steps=nk.stats.newton_steps, residuals=nk.stats.residuals, mu=nk.mu)
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t0
+    out["final_residual_Ha"] = out["residuals"][-1] if out["residuals"] else None
+    out["converged"] = bool(out["final_residual_Ha"] is not None and out["final_residual_Ha"] < args.tol)
+    return out
+
+
 def compare_solvers(path, wl, tol):
     """Damped fixed point, Pulay DIIS and Newton-Krylov (GMRES(20)) to
     max |Sigma[G(x)] - x| < tol, all on the fp64 path; the fixed point and
@@ -320,51 +364,117 @@ def compare_solvers(path, wl, tol):
             "gflop_per_sigma_evaluation": flops / 1e9}
 
 
-def compare_precisions(path64, V, H0, S, wl, tol):
-    """Whole self-consistent solves to max |Sigma[G(x)] - x| < tol from G0:
-    the plain damped fp64 loop, DIIS in fp64 and DIIS in the mixed path
-    (complex64 V, fp32 MFMA contractions); seconds, evaluations, and how far
-    the mixed fixed point lies from the fp64 one (equal-accuracy check)."""
+def presolve(path, tol, max_evals=40):
+    """Canonical DIIS (mu searched for N_target at every residual) from G0 to
+    max |F| < tol; returns copies of (Sigma_inf, Sigma~(tau)) and mu.  It
+    fixes the chemical potential of the grand-canonical solves that follow."""
+    from paper_2206_07660_amd.diis import DIIS
+    keep = path.fixed_mu
+    path.fixed_mu = False
+    try:
+        s0 = path.start(0.0)
+        dz = DIIS(path, depth=6)
+        x, F = dz.solve(s0.sig_inf, s0.sig_tau, s0.mu, tol=tol, max_iter=max_evals,
+                        log=lambda m: log(f"[presolve] {m}"))
+    finally:
+        path.fixed_mu = keep
+    return dz.inf(x).clone(), dz.tau(x).clone(), dz.mu, dz.stats.evaluations
+
+
+def begin(path, start):
+    """Scheme start: G0 at the mu of N_target (start None), or the state
+    (Sigma_inf, Sigma~, mu) of a pre-solve with its G at that mu."""
+    from paper_2206_07660_amd import gw
+    if start is None:
+        return path.start(0.0)
+    st = path.start(start[2], search=False)
+    gw.gw_axpby(path.ctx, 1.0, start[0], 0.0, st.sig_inf)
+    gw.gw_axpby(path.ctx, 1.0, start[1], 0.0, st.sig_tau)
+    gw.gw_tau_to_iw(path.ctx, gw.GW_FERMION, st.sig_tau, path.sig_iw)
+    st.mu, st.n_e = path.green(st.sig_inf, path.sig_iw, start[2], st.G_iw, st.G_tau)
+    return st
+
+
+def compare_precisions(path64, V, H0, S, wl, tol, presolve_tol=1e-4):
+    """Whole self-consistent solves to max |Sigma[G(x)] - x| < tol: the plain
+    damped fp64 loop, DIIS and Newton-Krylov in fp64 and DIIS in the mixed
+    path (complex64 V, fp32 MFMA contractions); seconds, evaluations, and how
+    far the fixed points lie apart (equal-accuracy check).  With a
+    grand-canonical path64 (fixed_mu) every solver starts from one canonical
+    DIIS pre-solve to presolve_tol and holds its mu, so that all of them
+    converge to the same self-energy; otherwise each starts from G0 and
+    searches mu at every residual."""
     import torch
     from paper_2206_07660_amd import gw
     from paper_2206_07660_amd.diis import DIIS
+    from paper_2206_07660_amd.newton import NewtonKrylov
     from paper_2206_07660_amd.scgw import GWPath
-    out = {"metric": "scGW solve to equal residual: plain fp64 loop vs DIIS fp64 vs DIIS mixed",
-           "workload": wl.name, "tol_max_abs_residual_Ha": tol}
+    fixed = bool(path64.fixed_mu)
+    out = {"metric": "scGW solve to equal residual: plain fp64 loop vs DIIS and Newton-Krylov fp64 vs "
+                     "DIIS mixed",
+           "workload": wl.name, "tol_max_abs_residual_Ha": tol, "fixed_mu": fixed}
+    ctx32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision="fp32")
+    p32 = GWPath(ctx32, V.to(torch.complex64), H0, S, wl.n_target, fixed_mu=fixed)
+    start = None
+    if fixed:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        si, stau, mu, nev = presolve(path64, presolve_tol)
+        start = (si, stau, mu)
+        out["presolve"] = {"solver": "canonical DIIS (fp64)", "tol": presolve_tol, "sigma_evaluations": nev,
+                           "seconds": time.perf_counter() - t0, "mu": mu}
+    sols = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = path64.start(0.0)
+    st = begin(path64, start)
     n_fp = 0
     while n_fp < 80:
         path64.step(st)
         n_fp += 1
-        log(f"[precisions] fp64 damped {n_fp}: dSigma {st.dsig:.3e}")
+        log(f"[precisions] fp64 damped {n_fp}: dSigma {st.dsig:.3e} mu {st.mu:.10f} N_e {st.n_e:.10f}")
         if st.dsig < tol:
             break
     torch.cuda.synchronize()
     out["fp64_damped"] = {"iterations": n_fp, "sigma_evaluations": n_fp,
-                          "seconds": time.perf_counter() - t0, "final_dsigma": st.dsig}
-    fp_inf, fp_tau = st.sig_inf.clone(), st.sig_tau.clone()
-    sols = {}
-    ctx32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision="fp32")
-    p32 = GWPath(ctx32, V.to(torch.complex64), H0, S, wl.n_target)
+                          "seconds": time.perf_counter() - t0, "final_dsigma": st.dsig, "mu": st.mu,
+                          "n_e": st.n_e}
+    sols["fp64_damped"] = (st.sig_inf.clone(), st.sig_tau.clone())
     for name, p in (("fp64_diis", path64), ("mixed_diis", p32)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s0 = p.start(0.0)
+        s0 = begin(p, start)
         dz = DIIS(p, depth=6)
         x, F = dz.solve(s0.sig_inf, s0.sig_tau, s0.mu, tol=tol, max_iter=60,
                         log=lambda m, n=name: log(f"[precisions] {n} {m}"))
         torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
         sols[name] = (dz.inf(x).clone(), dz.tau(x).clone())
         out[name] = {"iterations": dz.stats.iterations, "sigma_evaluations": dz.stats.evaluations,
-                     "seconds": sec, "residuals": dz.stats.residuals, "mu": dz.mu}
+                     "seconds": time.perf_counter() - t0, "residuals": dz.stats.residuals, "mu": dz.mu,
+                     "n_e": dz.n_e}
+    # Newton-Krylov (GMRES(20), stored P~) on the fp64 path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s0 = begin(path64, start)
+    nev0 = 0
+    if start is None:
+        for _ in range(2):
+            path64.step(s0)
+        nev0 = 2
+    nk = NewtonKrylov(path64, restart=20, gmres_rtol=1e-3)
+    x, F = nk.solve(s0.sig_inf, s0.sig_tau, s0.mu, tol=tol, max_steps=12,
+                    log=lambda m: log(f"[precisions] nk {m}"))
+    torch.cuda.synchronize()
+    sols["fp64_nk"] = (nk.inf(x).clone(), nk.tau(x).clone())
+    out["fp64_nk"] = {"newton_steps": nk.stats.newton_steps, "sigma_evaluations": nk.stats.evaluations + nev0,
+                      "jvps": nk.stats.jvps, "seconds": time.perf_counter() - t0,
+                      "residuals": nk.stats.residuals, "mu": nk.mu}
     d = lambda a, b: max((a[0] - b[0]).abs().max().item(), (a[1] - b[1]).abs().max().item())
-    out["max_abs_sigma_fp64_diis_vs_damped_Ha"] = d(sols["fp64_diis"], (fp_inf, fp_tau))
+    ref = sols["fp64_damped"]
+    out["max_abs_sigma_fp64_diis_vs_damped_Ha"] = d(sols["fp64_diis"], ref)
+    out["max_abs_sigma_fp64_nk_vs_damped_Ha"] = d(sols["fp64_nk"], ref)
     out["max_abs_sigma_mixed_vs_fp64_Ha"] = d(sols["mixed_diis"], sols["fp64_diis"])
-    out["speedup_fp64_diis_over_damped"] = out["fp64_damped"]["seconds"] / out["fp64_diis"]["seconds"]
-    out["speedup_mixed_diis_over_damped"] = out["fp64_damped"]["seconds"] / out["mixed_diis"]["seconds"]
+    for k in ("fp64_diis", "mixed_diis", "fp64_nk"):
+        out[f"speedup_{k}_over_damped"] = out["fp64_damped"]["seconds"] / out[k]["seconds"]
     out["speedup_mixed_over_fp64_diis"] = out["fp64_diis"]["seconds"] / out["mixed_diis"]["seconds"]
     ctx32.close()
     return out
@@ -393,6 +503,18 @@ def main():
                     help="instead of the step benchmark: plain fp64 damped loop vs DIIS in fp64 "
                          "and in mixed precision to --tol-mixed (default workload si-4x4x4)")
     ap.add_argument("--tol-mixed", type=float, default=1e-6)
+    ap.add_argument("--fixed-mu", action="store_true",
+                    help="grand-canonical solves: mu found for N_target at G0, then held")
+    ap.add_argument("--solve", choices=["damped", "diis", "nk"],
+                    help="instead of the step benchmark: one self-consistent solve to --tol")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the --solve path")
+    ap.add_argument("--ir", action="store_true", help="--solve on IR grids (lambda = beta * --ir-wmax)")
+    ap.add_argument("--per-q", action="store_true", help="Newton-Krylov with P~ rebuilt per q")
+    ap.add_argument("--max-evals", type=int, default=40)
+    ap.add_argument("--presolve-tol", type=float, default=1e-4,
+                    help="with --fixed-mu: canonical DIIS to this residual fixes mu")
+    ap.add_argument("--max-seconds", type=float, default=0.0)
     ap.add_argument("--oracle-timings", action="store_true",
                     help="instead of the step benchmark: time whole oracle evaluations on the CPU "
                          "(tiny-2x2x2 all threads and one thread, ad-3x3x3 all threads)")
@@ -425,24 +547,47 @@ def main():
     t0 = time.time()
     H0 = torch.from_numpy(inp.make_H0(wl)).to(dev)
     S = torch.from_numpy(inp.make_S(wl)).to(dev)
-    V = torch.empty((wl.nk, wl.nk, wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=dev)
+    vdt = torch.complex64 if (args.solve and args.precision == "fp32") else torch.complex128
+    V = torch.empty((wl.nk, wl.nk, wl.naux, wl.nao, wl.nao), dtype=vdt, device=dev)
     nthr = min(16, os.cpu_count() or 1)
     with ThreadPoolExecutor(nthr) as ex:
         for q, slab in enumerate(ex.map(lambda q: inp.make_V_slab(wl, q), range(wl.nk))):
             V[q].copy_(torch.from_numpy(slab))
     torch.cuda.synchronize()
-    log(f"[bench] inputs resident in HBM ({V.numel() * 16 / 1e9:.2f} GB V) after {time.time() - t0:.1f} s")
+    log(f"[bench] inputs resident in HBM ({V.numel() * V.element_size() / 1e9:.2f} GB V) after "
+        f"{time.time() - t0:.1f} s")
+    if args.solve:
+        ctx = gw.Context(wl.mesh, wl.nao, wl.naux, None if args.ir else wl.ntau, wl.beta, ns=wl.ns,
+                         precision=args.precision, ir=(wl.beta * args.ir_wmax, args.ir_eps) if args.ir else None)
+        path = GWPath(ctx, V, H0, S, wl.n_target, alpha=0.5, fixed_mu=args.fixed_mu)
+        start, pre = None, None
+        if args.fixed_mu:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            si, stau, mu, nev = presolve(path, args.presolve_tol)
+            start = (si, stau, mu)
+            pre = {"solver": "canonical DIIS", "tol": args.presolve_tol, "sigma_evaluations": nev,
+                   "seconds": time.perf_counter() - t0, "mu": mu}
+        res = solve(path, wl, args, start)
+        res["presolve"] = pre
+        res.update(workload=wl.name, precision=args.precision, fixed_mu=args.fixed_mu,
+                   grids=("IR lambda %g eps %g" % (wl.beta * args.ir_wmax, args.ir_eps)) if args.ir
+                   else "Chebyshev", ntau=ctx.ntau, tol=args.tol, n_target=wl.n_target)
+        print(json.dumps(res), flush=True)
+        ctx.close()
+        return
 
     ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns)
     log(f"[bench] grids built, tau chunk {ctx.tau_chunk}, workspace "
         f"{ctx.workspace.numel() / 1e9:.1f} GB after {time.time() - t0:.1f} s")
-    path = GWPath(ctx, V, H0, S, wl.n_target, alpha=0.5)
+    path = GWPath(ctx, V, H0, S, wl.n_target, alpha=0.5,
+                  fixed_mu=args.fixed_mu and (args.compare_solvers or args.compare_precisions))
     if args.compare_solvers:
         print(json.dumps(compare_solvers(path, wl, args.tol)), flush=True)
         ctx.close()
         return
     if args.compare_precisions:
-        print(json.dumps(compare_precisions(path, V, H0, S, wl, args.tol_mixed)), flush=True)
+        print(json.dumps(compare_precisions(path, V, H0, S, wl, args.tol_mixed, args.presolve_tol)), flush=True)
         ctx.close()
         return
     st = path.start(0.0)

@@ -6,7 +6,7 @@ reading here is Pulay's direct inversion in the iterative subspace on the
 same unknown and residual as the Newton-Krylov solver:
     x = (Sigma_inf, Sigma~(tau)),   F(x) = Sigma_GW[G(x)] - x,
 with G(x) from the Dyson equation at the chemical potential of the target
-electron count.  From the last m pairs (x_i, F_i) the coefficients c minimise
+electron count (or at a fixed mu with a grand-canonical path, GWPath(fixed_mu=True)).  From the last m pairs (x_i, F_i) the coefficients c minimise
 |sum_i c_i F_i|_2 under sum_i c_i = 1, and the next point is
     x_new = sum_i c_i (x_i + a F_i)  (a = 1: x_new = sum_i c_i Sigma_GW[G(x_i)]).
 The residuals are Hermitian per (tau, k), so the coefficients are taken real
@@ -153,8 +153,7 @@ class DIIS:
         """F = Sigma_GW[G(x)] - x (mu searched for the target N_e)."""
         gw, c, p = self.gw, self.ctx, self.path
         gw.gw_tau_to_iw(c, gw.GW_FERMION, self.tau(x), self.sig_iw)
-        self.mu, self.n_e = gw.gw_find_mu(c, p.H0, p.S, self.inf(x), self.sig_iw, p.n_target, self.mu,
-                                          G_iw=self.G_iw, G_tau=self.G_tau)
+        self.mu, self.n_e = p.green(self.inf(x), self.sig_iw, self.mu, self.G_iw, self.G_tau)
         p.sigma(self.G_tau, self.inf(F), self.tau(F))
         self.stats.evaluations += 1
         gw.gw_axpby(c, -1.0, x, 1.0, F)

@@ -3,7 +3,8 @@
 The unknown is x = (Sigma_inf, Sigma~(tau)) and the residual is
     F(x) = Sigma_GW[G(x)] - x,
 where G(x) solves the Dyson equation (Eq. Dyson) at the chemical potential
-that gives the target electron count (Sec. IV.A), and Sigma_GW is the
+that gives the target electron count (Sec. IV.A) or, with a grand-canonical
+path (GWPath(fixed_mu=True)), at a fixed mu, and Sigma_GW is the
 Hartree-Fock + dynamical GW self-energy (Eqs. HF_J, HF_K, tilde_sigma2).
 Each Newton step solves J_F(x) d = -F(x) with restarted GMRES; a Jacobian-
 vector product is the Dyson JVP (with the mu shift that keeps N_e fixed)
@@ -41,7 +42,7 @@ class NewtonKrylov:
         # system at low temperature N_e hardly depends on mu inside the gap,
         # so the shift that keeps N_e fixed is a ratio of two exponentially
         # small numbers, while G itself hardly depends on mu there either.
-        self.fixed_mu_jvp = fixed_mu_jvp
+        self.fixed_mu_jvp = fixed_mu_jvp or getattr(path, "fixed_mu", False)
         self.last_dmu = 0.0
         self.path = path
         self.ctx = path.ctx
@@ -80,8 +81,7 @@ class NewtonKrylov:
         """F = Sigma_GW[G(x)] - x; keeps G(x) and P~ of G(x) for the JVPs."""
         c, p = self.ctx, self.path
         gw.gw_tau_to_iw(c, gw.GW_FERMION, self.tau(x), self.sig_iw)
-        self.mu, _ = gw.gw_find_mu(c, p.H0, p.S, self.inf(x), self.sig_iw, p.n_target, self.mu,
-                                   G_iw=self.G_iw, G_tau=self.G_tau)
+        self.mu, _ = p.green(self.inf(x), self.sig_iw, self.mu, self.G_iw, self.G_tau)
         s_inf, s_tau, self.Pt_tau, self.Pt_iw = self.der.forward(self.G_tau)
         self.stats.evaluations += 1
         self.pack(s_inf, s_tau, F)

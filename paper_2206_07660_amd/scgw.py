@@ -37,8 +37,12 @@ class GWPath:
     corrections of Eqs. K_corr and GW_head_corr (gw_finite_size)."""
 
     def __init__(self, ctx: gw.Context, V, H0, S, n_target, alpha=0.5, hermitian=True,
-                 finite_size=None, want_phi=False):
+                 finite_size=None, want_phi=False, fixed_mu=False):
         self.ctx, self.V, self.H0, self.S = ctx, V, H0, S
+        # fixed_mu: grand-canonical iteration.  After start() has found the mu
+        # of n_target for G0, every Green's function is the Dyson solution at
+        # that mu (no search); the electron count is reported, not imposed.
+        self.fixed_mu = bool(fixed_mu)
         # want_phi: sigma() takes the screened-interaction solve through
         # gw_screened_W_phi and keeps Phi~ (Eq. tilde_Phi_GW) of that G in self.phi
         self.want_phi, self.phi = bool(want_phi), float("nan")
@@ -74,16 +78,34 @@ class GWPath:
             gw.gw_finite_size(c, self.S, chi, self.gamma, out_inf, G_tau, head, out_tau)
         return out_inf, out_tau
 
+    def green(self, sig_inf, sig_iw, mu, G_iw, G_tau):
+        """G(i w) and G(tau) of the self-energy: at the mu of n_target
+        (gw_find_mu from mu), or at mu itself when fixed_mu.  Returns (mu, N_e)."""
+        c = self.ctx
+        if not self.fixed_mu:
+            return gw.gw_find_mu(c, self.H0, self.S, sig_inf, sig_iw, self.n_target, mu,
+                                 G_iw=G_iw, G_tau=G_tau)
+        gw.gw_dyson_G(c, self.H0, self.S, sig_inf, sig_iw, mu, G_iw)
+        gw.gw_iw_to_tau(c, gw.GW_FERMION, G_iw, G_tau)
+        return mu, gw.gw_density(c, G_tau, self.S, self.gamma)
+
     # ------------------------------------------------ scGW loop -----------
-    def start(self, mu0=0.0):
+    def start(self, mu0=0.0, search=True):
+        """Sigma = 0 and G0 at the mu of n_target (searched from mu0), or at mu0
+        itself with search=False."""
         c = self.ctx
         z = dict(dtype=torch.complex128, device="cuda")
         st = State(mu0, torch.empty(c.k_shape(), **z), torch.empty(c.g_shape(), **z),
                    torch.empty(c.g_shape(), **z), torch.empty(c.giw_shape(), **z))
         gw.gw_mix(c, 1.0, None, st.sig_inf)
         gw.gw_mix(c, 1.0, None, st.sig_tau)
-        st.mu, st.n_e = gw.gw_find_mu(c, self.H0, self.S, None, None, self.n_target, mu0,
-                                      G_iw=st.G_iw, G_tau=st.G_tau)
+        if search:
+            st.mu, st.n_e = gw.gw_find_mu(c, self.H0, self.S, None, None, self.n_target, mu0,
+                                          G_iw=st.G_iw, G_tau=st.G_tau)
+        else:
+            gw.gw_dyson_G(c, self.H0, self.S, None, None, mu0, st.G_iw)
+            gw.gw_iw_to_tau(c, gw.GW_FERMION, st.G_iw, st.G_tau)
+            st.n_e = gw.gw_density(c, st.G_tau, self.S, self.gamma)
         return st
 
     def step(self, st: State, want_diff=True):
@@ -93,8 +115,7 @@ class GWPath:
         d1 = gw.gw_mix(c, self.alpha, self.new_inf, st.sig_inf, want_diff)
         d2 = gw.gw_mix(c, self.alpha, self.new_tau, st.sig_tau, want_diff)
         gw.gw_tau_to_iw(c, gw.GW_FERMION, st.sig_tau, self.sig_iw)
-        st.mu, st.n_e = gw.gw_find_mu(c, self.H0, self.S, st.sig_inf, self.sig_iw, self.n_target,
-                                      st.mu, G_iw=st.G_iw, G_tau=st.G_tau)
+        st.mu, st.n_e = self.green(st.sig_inf, self.sig_iw, st.mu, st.G_iw, st.G_tau)
         st.dsig = max(d1, d2) if want_diff else float("nan")
         st.iteration += 1
         return st

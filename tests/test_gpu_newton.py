@@ -219,3 +219,52 @@ def test_diis_fixed_point_matches_oracle_scgw():
         assert d_inf < 1e-9 and d_tau < 1e-9 and abs(dz.mu - mu_r) < 1e-9
     finally:
         ctx.close()
+
+
+def test_grand_canonical_solvers_agree_with_oracle():
+    """At a fixed mu (GWPath(fixed_mu=True)) the damped loop, DIIS and
+    Newton-Krylov reach one self-energy, the oracle's fixed-mu damped scGW
+    fixed point; the electron count is then an output."""
+    from oracle import grids as og
+    from oracle import gw as ogw
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.diis import DIIS
+    from paper_2206_07660_amd.newton import NewtonKrylov
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(mesh=(2, 2, 1), nao=4, naux=12, ntau=12, beta=10.0, seed=31, n_target=4.0)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    mu = 0.05
+    g = og.Grids(wl.beta, wl.ntau)
+    hist = ogw.scgw(H0, S, V, g, wl.mesh, NS, None, 150, mu0=mu)
+    (_, si_a, st_a, _), (mu_r, si_r, st_r, G_r) = hist[-2], hist[-1]
+    assert max(np.abs(si_r - si_a).max(), np.abs(st_r - st_a).max()) < 1e-12 and mu_r == mu
+    n_r = ogw.electron_count(ogw.density_matrix(G_r, g.w), S, NS)
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS)
+    try:
+        path = GWPath(ctx, dev(V), dev(H0), dev(S), wl.n_target, fixed_mu=True)
+        st = path.start(mu, search=False)
+        n_fp = 0
+        while n_fp < 200:
+            path.step(st)
+            n_fp += 1
+            if st.dsig < 1e-12:
+                break
+        assert st.mu == mu and abs(st.n_e - n_r) < 1e-10
+        sols = {"damped": (st.sig_inf.cpu().numpy(), st.sig_tau.cpu().numpy())}
+        s0 = path.start(mu, search=False)
+        dz = DIIS(path, depth=6)
+        x, F = dz.solve(s0.sig_inf, s0.sig_tau, mu, tol=1e-12, max_iter=60)
+        sols["diis"] = (dz.inf(x).cpu().numpy(), dz.tau(x).cpu().numpy())
+        s0 = path.start(mu, search=False)
+        nk = NewtonKrylov(path, restart=20, gmres_rtol=1e-8)
+        assert nk.fixed_mu_jvp
+        x, F = nk.solve(s0.sig_inf, s0.sig_tau, mu, tol=1e-12, max_steps=15)
+        sols["nk"] = (nk.inf(x).cpu().numpy(), nk.tau(x).cpu().numpy())
+        for name, (a, b) in sols.items():
+            d = max(np.abs(a - si_r).max(), np.abs(b - st_r).max())
+            print(f"fixed mu {name}: |Sigma - oracle| {d:.2e}")
+            assert d < 1e-10, name
+        print(f"evaluations: damped {n_fp}, DIIS {dz.stats.evaluations}, NK {nk.stats.evaluations} + "
+              f"{nk.stats.jvps} JVPs; N_e {st.n_e:.12f}")
+    finally:
+        ctx.close()
