@@ -514,6 +514,7 @@ def main():
     ap.add_argument("--max-evals", type=int, default=40)
     ap.add_argument("--presolve-tol", type=float, default=1e-4,
                     help="with --fixed-mu: canonical DIIS to this residual fixes mu")
+    ap.add_argument("--presolve-max-evals", type=int, default=40)
     ap.add_argument("--max-seconds", type=float, default=0.0)
     ap.add_argument("--oracle-timings", action="store_true",
                     help="instead of the step benchmark: time whole oracle evaluations on the CPU "
@@ -564,7 +565,7 @@ def main():
         if args.fixed_mu:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            si, stau, mu, nev = presolve(path, args.presolve_tol)
+            si, stau, mu, nev = presolve(path, args.presolve_tol, args.presolve_max_evals)
             start = (si, stau, mu)
             pre = {"solver": "canonical DIIS", "tol": args.presolve_tol, "sigma_evaluations": nev,
                    "seconds": time.perf_counter() - t0, "mu": mu}
