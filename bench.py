@@ -142,10 +142,12 @@ def cpu_baseline(wl, ntau_sample):
             "seconds_per_eval_extrapolated": t_eval, "host": host_info()}
 
 
-def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
-    """One Sigma+Pi evaluation from the current G in fp64 and in the mixed
-    path (complex64 V, fp32 MFMA contractions, fp64 elsewhere): seconds each
-    and the max-abs difference of Sigma_inf and Sigma~ in Ha."""
+def mixed_comparison(ctx64, path64, st, V, H0, S, wl, precision="fp32"):
+    """One Sigma+Pi evaluation from the current G in fp64 and in a mixed
+    path (complex64 V; "fp32": fp32 MFMA contractions, "bf16x3": split-bf16
+    MFMA for the two large contractions and fp32 for the producers and the
+    final self-energy contraction; fp64 elsewhere): seconds each and the
+    max-abs difference of Sigma_inf and Sigma~ in Ha."""
     import torch
     from paper_2206_07660_amd import gw
     from paper_2206_07660_amd.scgw import GWPath
@@ -157,7 +159,7 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
     t64 = time.perf_counter() - t0
     ref_inf, ref_tau = s64_inf.clone(), s64_tau.clone()
     V32 = V.to(torch.complex64)
-    ctx32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision="fp32")
+    ctx32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision=precision)
     p32 = GWPath(ctx32, V32, H0, S, wl.n_target)
     p32.sigma(G)                                   # warm-up
     torch.cuda.synchronize()
@@ -172,19 +174,25 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl):
     e_tau = (s32_tau - ref_tau).abs().max().item()
     flops = contraction_flops(wl.nk, wl.nao, wl.naux, wl.ntau)
     n_l, ms_l, fl_l = prof["pol_contract"]
+    n_s, ms_s, fl_s = prof["se_contract"]
+    how = ("fp32 MFMA with fp64 chunk sums" if precision == "fp32" else
+           "split-bf16 (bf16x3) MFMA for the polarization and P~ V contractions, fp32 MFMA for the "
+           "producers and the final self-energy contraction, fp64 chunk sums")
     res = {"sigma_eval_s_fp64": t64, "sigma_eval_s_mixed": t32, "speedup": t64 / t32,
            "evals_per_s_mixed": 1.0 / t32,
            "gflops_contractions_mixed": flops / t32 / 1e9,
-           "fp32_mfma_frac_path": flops / t32 / 157.3e12,
            "pol_contract_tflops_mixed": fl_l / (ms_l * 1e-3) / 1e12 if ms_l else None,
+           "se_contract_tflops_mixed": fl_s / (ms_s * 1e-3) / 1e12 if ms_s else None,
            "max_abs_dSigma_inf_Ha": e_inf, "max_abs_dSigma_tilde_Ha": e_tau,
            "kernel_ms": {k: round(v[1], 2) for k, v in prof.items() if v[0]},
-           "precision": "V complex64, G rounded to complex64, fp32 MFMA with fp64 chunk sums; "
-                        "transforms, screened-interaction solve, HF, Dyson, mu in fp64"}
+           "precision": "V complex64, G rounded to complex64, " + how +
+                        "; transforms, screened-interaction solve, HF, Dyson, mu in fp64"}
+    if precision == "fp32":
+        res["fp32_mfma_frac_path"] = flops / t32 / 157.3e12
     ctx32.close()
     del V32, p32
     torch.cuda.empty_cache()
-    log(f"[bench] mixed: {t32:.2f} s vs fp64 {t64:.2f} s per Sigma+Pi evaluation, "
+    log(f"[bench] mixed {precision}: {t32:.2f} s vs fp64 {t64:.2f} s per Sigma+Pi evaluation, "
         f"max|dSigma| {max(e_inf, e_tau):.2e} Ha")
     return res
 
@@ -507,7 +515,7 @@ def main():
                     help="grand-canonical solves: mu found for N_target at G0, then held")
     ap.add_argument("--solve", choices=["damped", "diis", "nk"],
                     help="instead of the step benchmark: one self-consistent solve to --tol")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="precision of the --solve path")
     ap.add_argument("--ir", action="store_true", help="--solve on IR grids (lambda = beta * --ir-wmax)")
     ap.add_argument("--per-q", action="store_true", help="Newton-Krylov with P~ rebuilt per q")
@@ -548,7 +556,7 @@ def main():
     t0 = time.time()
     H0 = torch.from_numpy(inp.make_H0(wl)).to(dev)
     S = torch.from_numpy(inp.make_S(wl)).to(dev)
-    vdt = torch.complex64 if (args.solve and args.precision == "fp32") else torch.complex128
+    vdt = torch.complex64 if (args.solve and args.precision != "fp64") else torch.complex128
     V = torch.empty((wl.nk, wl.nk, wl.naux, wl.nao, wl.nao), dtype=vdt, device=dev)
     nthr = min(16, os.cpu_count() or 1)
     with ThreadPoolExecutor(nthr) as ex:
@@ -657,7 +665,8 @@ def main():
         "history": hist,
     }
     if not args.no_mixed:
-        out["mixed_fp32"] = mixed_comparison(ctx, path, st, V, H0, S, wl)
+        out["mixed_fp32"] = mixed_comparison(ctx, path, st, V, H0, S, wl, "fp32")
+        out["mixed_bf16x3"] = mixed_comparison(ctx, path, st, V, H0, S, wl, "bf16x3")
     if not args.no_ir:
         out["ir_grids"] = ir_comparison(path, V, H0, S, wl, wl.beta * args.ir_wmax, args.ir_eps, ms_step)
     if not args.no_cpu_baseline:

@@ -78,8 +78,14 @@ enum { GW_FERMION = 0, GW_BOSON = 1 };
  *   accumulated in fp32 into fp64; their outputs (P0, Sigma~) are
  *   complex128.  gw_hf reads the complex64 V in fp64 arithmetic; the
  *   transforms, both Dyson solves and the mu search are fp64 as in
- *   GW_PREC_FP64.                                                           */
-enum { GW_PREC_FP64 = 0, GW_PREC_FP32 = 1 };
+ *   GW_PREC_FP64.
+ * GW_PREC_BF16X3: as GW_PREC_FP32, except that the two large contractions
+ *   (sum over (k, d, b) of Eq. tilde_P0_tau, and P~ V of Eq. tilde_sigma2)
+ *   run on bf16 MFMA with split operands: each real operand x is held as
+ *   hi + lo, hi = bf16(x), lo = bf16(x - hi), and each real product as
+ *   a_hi b_hi + a_hi b_lo + a_lo b_hi (relative error near 2^-16 per
+ *   product), with fp32 accumulation and fp64 sums of 512-term chunks.     */
+enum { GW_PREC_FP64 = 0, GW_PREC_FP32 = 1, GW_PREC_BF16X3 = 2 };
 typedef struct { float re, im; } gw_c;
 
 typedef struct {
@@ -207,7 +213,7 @@ gw_status gw_set_workspace(gw_ctx* ctx, void* dev, size_t bytes, int tau_chunk);
  *                       V^{k+q,k}_{bc}(Q') G^k_{cd}(tau_{ntau-1-i})
  * for q = q0 .. q0+nq-1, written to P0_tau[q-q0][i] (overwritten).          */
 gw_status gw_polarization(gw_ctx* ctx, const void* V, const gw_z* G_tau, int q0, int nq,
-                          gw_z* P0_tau);   /* V: gw_z (GW_PREC_FP64) or gw_c (GW_PREC_FP32) */
+                          gw_z* P0_tau);   /* V: gw_z (GW_PREC_FP64) or gw_c (the other modes) */
 
 /* gw_polarization for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
@@ -218,7 +224,8 @@ gw_status gw_polarization(gw_ctx* ctx, const void* V, const gw_z* G_tau, int q0,
  * made through it are not counted by gw_profile_read).  The tau chunk is the
  * largest that fits the scratch; if one tau slice of the intermediates does
  * not fit (fp64: 32 Nk naux nao^2 bytes > 128 MiB; fp32: 16 Nk naux nao^2 +
- * 16 ntau Nk nao^2 bytes) the call returns GW_ERR_WORKSPACE and launches
+ * 16 ntau Nk nao^2 bytes; bf16x3 about the fp32 figure plus 8 Nk nao^2
+ * naux' + 8 naux naux', naux' = naux rounded up to 32) the call returns GW_ERR_WORKSPACE and launches
  * nothing.  Every call on one GPU shares that GPU's scratch, whatever the
  * context: calls that overlap in time on one GPU (different streams or host
  * threads) race and give undefined results.  Other arguments and errors as

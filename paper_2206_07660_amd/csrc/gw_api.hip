@@ -43,6 +43,8 @@ struct gw_ctx {
   std::vector<int> plus;   // host copy of the k+q table
   bool check_bounds = false;
   int tile_cfg = -1;       // tile configuration of the large contractions (-1: default)
+  int split_cfg = -1;      // tile configuration of the split-bf16 contractions
+  int split_group = 0;     // > 0: grouped workgroup order of the split contractions
   int herm = 0;            // gw_set_hermitian: GW_HERM_* bits
   double mu_window = 0.0;  // gw_set_mu_window: electron-count window (0: exact root)
   // measurement: event pairs per kernel class while profiling is on
@@ -100,7 +102,7 @@ gw_status check_dims(const gw_dims* d, std::string& why) {
   }
   if (d->ns != 1 && d->ns != 2) { why = "ns must be 1 or 2"; return GW_ERR_ARG; }
   if (!(d->beta > 0.0) || !std::isfinite(d->beta)) { why = "beta must be positive"; return GW_ERR_ARG; }
-  if (d->precision != GW_PREC_FP64 && d->precision != GW_PREC_FP32) {
+  if (d->precision != GW_PREC_FP64 && d->precision != GW_PREC_FP32 && d->precision != GW_PREC_BF16X3) {
     why = "unsupported precision";
     return GW_ERR_ARG;
   }
@@ -224,6 +226,42 @@ gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
   return prof_end(c, g.tag, e0, 8.0 * outs * g.K * g.batch);
 }
 
+// Split-bf16 contraction: eA, eB, eC the valid element ranges of the
+// operands; k_true the K that the algorithmic flops count.
+gw_status run_split(gw_ctx* c, const SplitDesc& d, Ext eA, Ext eB, Ext eC) {
+  if (c->check_bounds) {
+    auto span = [&](const Map3& bm, const Map3& rm, int rows, long long ks, long long& lo, long long& hi) {
+      long long l1, h1, l2, h2;
+      map_range(bm, d.batch, l1, h1);
+      map_range(rm, rows, l2, h2);
+      lo = l1 + l2 + std::min(0LL, (long long)(d.K - 1) * ks);
+      hi = h1 + h2 + std::max(0LL, (long long)(d.K - 1) * ks);
+    };
+    long long la, ha, lb, hb, lc, hc, l1, h1;
+    span(d.ba, d.am, d.M, d.aks, la, ha);
+    span(d.bb, d.bn, d.N, d.bks, lb, hb);
+    span(d.bc, d.cm, d.M, 0, lc, hc);
+    map_range(d.cn, d.N, l1, h1);
+    lc += l1;
+    hc += h1;
+    if (la < eA.lo || ha >= eA.hi || lb < eB.lo || hb >= eB.hi || lc < eC.lo || hc >= eC.hi)
+      return fail(c, GW_ERR_ARG, "internal descriptor check: split contraction out of bounds");
+  }
+  hipEvent_t e0 = nullptr;
+  gw_status s = prof_begin(c, d.tag, &e0);
+  if (s != GW_OK) return s;
+  SplitDesc dd = d;
+  dd.cfg = c->split_cfg;
+  if (c->split_group > 0) {
+    dd.batch_fastest = 2;
+    dd.group = c->split_group;
+  }
+  hipError_t e = bsgemm_launch(dd, c->st);
+  if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("bsgemm: ") + hipGetErrorString(e));
+  const double outs = d.tri ? 0.5 * d.M * (d.M + 1.0) : (double)d.M * d.N;
+  return prof_end(c, d.tag, e0, 8.0 * outs * d.K * d.batch);
+}
+
 gw_status read_flag(gw_ctx* c, const char* what) {
   int f = 0;
   HIPCHK(c, hipMemcpyAsync(&f, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -316,6 +354,10 @@ gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
     c->check_bounds = e && e[0] == '1';
     const char* t = std::getenv("GW_TILE_CFG");
     c->tile_cfg = t ? std::atoi(t) : -1;
+    const char* u = std::getenv("GW_SPLIT_CFG");
+    c->split_cfg = u ? std::atoi(u) : -1;
+    const char* gg = std::getenv("GW_SPLIT_GROUP");
+    c->split_group = gg ? std::atoi(gg) : 0;
   }
   if (upload(c, &c->dplus, plus.data(), plus.size() * sizeof(int)) != GW_OK ||
       upload(c, &c->dminus, minus.data(), minus.size() * sizeof(int)) != GW_OK ||
@@ -593,10 +635,24 @@ gw_status gw_get_grids(const gw_ctx* cc, double* tau, long long* nF, long long* 
 // Bytes of the polarization / self-energy chains for a tau chunk: two
 // intermediates of tc x Nk x naux x nao^2 (plus complex64 copies of two G
 // arrays in mixed precision).
+// complex64 V and chain intermediates (GW_PREC_FP32, GW_PREC_BF16X3)
+static bool lowp(const gw_ctx* c) { return c->d.precision != GW_PREC_FP64; }
+// split-bf16 operands of the two large contractions (GW_PREC_BF16X3)
+static bool splitbf(const gw_ctx* c) { return c->d.precision == GW_PREC_BF16X3; }
+// Chain workspace: two tau-chunk regions (X and Zt, or Vt and L); in the
+// low-precision modes two complex64 copies of G after them.
+static size_t region_bytes(const gw_ctx* c, int tc) {
+  return align256((size_t)tc * c->nk * c->sv * (lowp(c) ? 8 : 16));
+}
+static size_t gslot_bytes(const gw_ctx* c) { return align256((size_t)c->d.ntau * c->nk * c->n2 * 8); }
+
+// complex64 P~ of one tau chunk (split mode, after the G copies)
+static size_t pchunk_bytes(const gw_ctx* c, int tc) {
+  return align256((size_t)tc * c->d.naux * (size_t)c->d.naux * 8);
+}
+
 static size_t chain_bytes(const gw_ctx* c, int tc) {
-  if (c->d.precision == GW_PREC_FP32)
-    return 2 * align256((size_t)tc * c->nk * c->sv * 8) + 2 * align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
-  return 2 * align256((size_t)tc * c->nk * c->sv * 16);
+  return 2 * region_bytes(c, tc) + (lowp(c) ? 2 * gslot_bytes(c) : 0) + (splitbf(c) ? pchunk_bytes(c, tc) : 0);
 }
 
 static size_t screened_bytes(const gw_ctx* c, int nq) {
@@ -741,8 +797,7 @@ static Work ctx_work(gw_ctx* c) { return Work{(char*)c->ws, c->ws_bytes, c->tc};
 
 // complex64 copy of G in slot 0 or 1 of the mixed-precision workspace
 static gw_status g_to_c64(gw_ctx* c, const Work& w, const gw_z* G, void** Gc, int slot = 0) {
-  const size_t off = 2 * align256((size_t)w.tc * c->nk * c->sv * 8) +
-                     (size_t)slot * align256((size_t)c->d.ntau * c->nk * c->n2 * 8);
+  const size_t off = 2 * region_bytes(c, w.tc) + (size_t)slot * gslot_bytes(c);
   *Gc = w.base + off;
   HIPCHK(c, to_c64_launch((const double2*)G, (float2*)*Gc, (long long)c->d.ntau * c->nk * c->n2, c->st));
   return GW_OK;
@@ -797,6 +852,61 @@ gw_status gw_polarization_noalloc(gw_ctx* c, const void* V, const gw_z* G, int q
   return s;
 }
 
+// One tau chunk of Eq. tilde_P0_tau in the split-bf16 mode (GW_PREC_BF16X3).
+// The complex64 producers write X and Zt with K = (k, d, b) contiguous per
+// row, so that the contraction's loader reads whole K-runs:
+//   X2[tl][Q][k n2 + d nao + b]  = sum_a V[q][k][Q][d][a] G[t0+tl][k+q][a][b]
+//   Z2[tl][Q'][k n2 + d nao + b] = sum_c G[nt-1-t0-tl][k][c][d] conj(V[q][k][Q'][c][b])
+//   P0[iq][t0+tl][Q][Q'] (+)= -(ns/nk) sum_K X2[tl][Q][K] Z2[tl][Q'][K]   (bf16x3)
+// Gd and Gbd are the complex64 copies of the two G slots.
+static gw_status pol_split_chunk(gw_ctx* c, const char* Aq, const char* Gd, const char* Gbd, char* X, char* Z,
+                                 int q, int iq, int t0, int tcur, int tc, gw_z* P0, bool accumulate,
+                                 bool herm) {
+  const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
+  const long long n2 = c->n2, sv = c->sv;
+  const long long K = (long long)nk * n2, ldr = (long long)naux * K;
+  GemmDesc g = gemm_desc();
+  g.A = Aq; g.B = Gd + (size_t)t0 * nk * n2 * 8; g.C = X;
+  g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
+  g.am = aff(nao); g.ak = aff(1);
+  g.bk = aff(nao); g.bn = two(nao, 1, (long long)nk * n2);
+  g.cm = two(nao, nao, K); g.cn = two(nao, 1, ldr);
+  g.ba = aff(sv); g.bb = aff(0); g.bc = aff(n2);
+  g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;   // G^{k+q}
+  g.ta = g.tb = g.tc = 1; g.f32 = 1;
+  g.tag = KC_POL_PRODUCER;
+  gw_status s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * ldr});
+  if (s != GW_OK) return s;
+  g = gemm_desc();
+  g.A = Gbd + (size_t)(nt - 1 - t0) * nk * n2 * 8; g.B = Aq; g.C = Z;
+  g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
+  g.am = two(nao, 1, -(long long)nk * n2); g.ak = aff(nao);
+  g.bk = aff(nao); g.bn = two(nao, 1, n2); g.conjB = 1;
+  g.cm = two(nao, nao, ldr); g.cn = two(nao, 1, K);
+  g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(n2);
+  g.ta = g.tb = g.tc = 1; g.f32 = 1;
+  g.tag = KC_POL_PRODUCER;
+  if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv},
+               Ext{0, (long long)tc * ldr})) != GW_OK)
+    return s;
+  SplitDesc d = split_desc();
+  d.A = X; d.B = Z; d.C = (double2*)P0 + ((long long)iq * nt + t0) * naux * naux;
+  d.M = naux; d.N = naux; d.K = (int)K; d.batch = tcur;
+  d.ta = d.tb = 1; d.tc = 0;
+  d.am = aff(K); d.aks = 1; d.bn = aff(K); d.bks = 1;
+  d.ba = d.bb = aff(ldr); d.bc = aff((long long)naux * naux);
+  d.cm = aff(naux); d.cn = aff(1);
+  d.alpha_r = -(double)c->d.ns / nk;
+  if (accumulate) { d.beta_zero = 0; d.beta_r = 1.0; }
+  d.tri = herm ? 1 : 0; d.kchunk = kMixedChunk;
+  d.tag = KC_POL_CONTRACT;
+  if ((s = run_split(c, d, Ext{0, (long long)tcur * ldr}, Ext{0, (long long)tcur * ldr},
+                     Ext{0, (long long)tcur * naux * naux})) != GW_OK)
+    return s;
+  if (herm) HIPCHK(c, herm_fill_launch((double2*)d.C, naux, tcur, c->st));
+  return GW_OK;
+}
+
 // G fills the tau slot (G^{k+q}(tau_i)), Gb the mirrored slot (G^k(tau_{ntau-1-i})).
 static gw_status pol_impl(gw_ctx* c, const Work& w, const void* V, const gw_z* G, const gw_z* Gb,
                           int q0, int nq, gw_z* P0, bool accumulate, bool two_slot) {
@@ -811,10 +921,11 @@ static gw_status pol_impl(gw_ctx* c, const Work& w, const void* V, const gw_z* G
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv;
   const long long S = (long long)nk * sv;                // one tau slice of X or Zt
-  const bool f32 = c->d.precision == GW_PREC_FP32;
+  const bool f32 = lowp(c);
+  const bool sb = splitbf(c);
   const size_t ez = f32 ? 8 : 16;                        // bytes of V / X / Zt / G elements
   char* X = w.base;
-  char* Z = w.base + align256((size_t)tc * S * ez);
+  char* Z = w.base + region_bytes(c, tc);
   const char* Vd = (const char*)V;
   const char* Gd = (const char*)G;
   const char* Gbd = (const char*)Gb;
@@ -838,6 +949,11 @@ static gw_status pol_impl(gw_ctx* c, const Work& w, const void* V, const gw_z* G
     const char* Aq = Vd + (size_t)q * nk * sv * ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {
       const int tcur = std::min(tc, nt - t0);
+      if (sb) {
+        gw_status s = pol_split_chunk(c, Aq, Gd, Gbd, X, Z, q, q - q0, t0, tcur, tc, P0, accumulate, herm);
+        if (s != GW_OK) return s;
+        continue;
+      }
       // X[tl][k][Q][d][b] = sum_a V[q][k][Q][d][a] G[t0+tl][k+q][a][b]
       GemmDesc g = gemm_desc();
       g.A = Aq; g.B = Gd + (size_t)t0 * nk * n2 * ez; g.C = X;
@@ -1018,10 +1134,11 @@ gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv;
   const long long S = (long long)nk * sv;
-  const bool f32 = c->d.precision == GW_PREC_FP32;
+  const bool f32 = lowp(c);
+  const bool sb = splitbf(c);
   const size_t ez = f32 ? 8 : 16;
   char* Vt = (char*)c->ws;
-  char* L = (char*)c->ws + align256((size_t)tc * S * ez);
+  char* L = (char*)c->ws + region_bytes(c, tc);
   const char* Vd = (const char*)V;
   const char* Gd = (const char*)G;
   if (f32) {
@@ -1038,23 +1155,46 @@ gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt
       const int tcur = std::min(tc, nt - t0);
       // Vt[tl][Q][kk][b][j] = sum_Q' Pt[q][t0+tl][Q][Q'] V[q][kk][Q'][b][j]
       // (fp64), or Vt[tl][kk][Q][b][j] (mixed): see the final contraction
-      GemmDesc g = gemm_desc();
-      g.A = (const double2*)Pt + ((long long)(q - q0) * nt + t0) * naux * naux;
-      g.B = Aq; g.C = Vt;
-      g.M = naux; g.N = nk * (int)n2; g.K = naux; g.batch = tcur;
-      g.am = aff(naux); g.ak = aff(1);
-      g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
-      if (kmajor) { g.cm = aff(n2); g.cn = two((unsigned)n2, 1, sv); }
-      else { g.cm = aff((long long)nk * n2); g.cn = aff(1); }
-      g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
-      g.ta = 0; g.tb = g.tc = t; g.f32 = t;
-      g.batch_fastest = 1;                      // every tau reads the same V slab
-      g.tag = KC_SE_CONTRACT;
-      gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
-      if (s != GW_OK) return s;
+      if (sb) {
+        // bf16x3: rows Q of P~ (complex64 copy, K = Q' contiguous), columns
+        // (kk, b, j) of the V slab read in place (K = Q' with stride n2)
+        float2* Pc = (float2*)((char*)c->ws + 2 * region_bytes(c, tc) + 2 * gslot_bytes(c));
+        HIPCHK(c, to_c64_launch((const double2*)Pt + ((long long)(q - q0) * nt + t0) * naux * naux, Pc,
+                                (long long)tcur * naux * naux, c->st));
+        SplitDesc d = split_desc();
+        d.A = Pc;
+        d.B = Aq; d.C = Vt;
+        d.M = naux; d.N = nk * (int)n2; d.K = naux; d.batch = tcur;
+        d.ta = 1; d.tb = 1; d.tc = 1;
+        d.am = aff(naux); d.aks = 1; d.ba = aff((long long)naux * naux);
+        d.bn = two((unsigned)n2, 1, sv); d.bks = n2; d.bb = aff(0);
+        d.cm = aff(n2); d.cn = two((unsigned)n2, 1, sv); d.bc = aff(S);
+        d.batch_fastest = 1;                    // every tau reads the same V slab
+        d.kchunk = kMixedChunk;
+        d.tag = KC_SE_CONTRACT;
+        gw_status s = run_split(c, d, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv},
+                                Ext{0, (long long)tcur * S});
+        if (s != GW_OK) return s;
+      } else {
+        GemmDesc g = gemm_desc();
+        g.A = (const double2*)Pt + ((long long)(q - q0) * nt + t0) * naux * naux;
+        g.B = Aq; g.C = Vt;
+        g.M = naux; g.N = nk * (int)n2; g.K = naux; g.batch = tcur;
+        g.am = aff(naux); g.ak = aff(1);
+        g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
+        if (kmajor) { g.cm = aff(n2); g.cn = two((unsigned)n2, 1, sv); }
+        else { g.cm = aff((long long)nk * n2); g.cn = aff(1); }
+        g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
+        g.ta = 0; g.tb = g.tc = t; g.f32 = t;
+        g.batch_fastest = 1;                      // every tau reads the same V slab
+        g.tag = KC_SE_CONTRACT;
+        gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
+        if (s != GW_OK) return s;
+      }
       // L[tl][kk][Q][i][b] (fp64) or L[tl][kk][i][Q][b] (mixed)
       //   = sum_a conj(V[q][kk][Q][a][i]) G[t0+tl][kk][a][b]
-      g = gemm_desc();
+      gw_status s;
+      GemmDesc g = gemm_desc();
       g.A = Aq; g.B = Gd + (size_t)t0 * nk * n2 * ez; g.C = L;
       g.M = naux * nao; g.N = tcur * nao; g.K = nao; g.batch = nk;
       g.am = two(nao, 1, n2); g.ak = aff(nao); g.conjA = 1;
@@ -1136,7 +1276,7 @@ gw_status gw_hf(gw_ctx* c, const void* V, const gw_z* G, gw_z* gamma_out, gw_z* 
   double2* vq = (double2*)((char*)gam + align256((size_t)nk * n2 * 16));
   if (gamma_out) gam = (double2*)gamma_out;
   const char* Vd = (const char*)V;
-  const int tv = c->d.precision == GW_PREC_FP32 ? 1 : 0;   // V storage type
+  const int tv = lowp(c) ? 1 : 0;   // V storage type
   const size_t ez = tv ? 8 : 16;
   gw_status s = gamma_of(c, G, gam);
   if (s != GW_OK) return s;

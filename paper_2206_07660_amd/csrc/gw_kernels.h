@@ -70,7 +70,9 @@ struct GemmDesc {
   int ta, tb, tc;   // storage types of A, B, C (0 complex128, 1 complex64)
   int f32;          // 1: fp32 MFMA with fp64 promotion every kchunk K-elements
   int kchunk;
-  int batch_fastest;  // workgroup order: 0 tile-fastest, 1 batch-fastest
+  int batch_fastest;  // workgroup order: 0 tile-fastest, 1 batch-fastest,
+                      // 2 batch-fastest over groups of `group` tiles
+  int group;
   int tri;            // 1: M == N and only the output tiles on or above the
                       // diagonal are computed (Hermitian products)
   // filled by the launcher: dividers of the workgroup-id decomposition
@@ -85,6 +87,43 @@ static inline GemmDesc gemm_desc() {
   d.alpha_r = 1.0;
   d.beta_zero = 1;
   d.batch = 1;
+  return d;
+}
+
+// Split-bf16 complex GEMM (bsgemm_k, bf16x3 with operands split in LDS):
+// C[b](m, n) = alpha * sum_k A[b](m, k) B[b](n, k) + beta * C[b](m, n) with
+// A(m, k) = A[ba(b) + am(m) + k aks] and B(n, k) = B[bb(b) + bn(n) + k bks].
+// Offsets count complex elements of the operand's storage type.
+struct SplitDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K, batch;
+  int ta, tb, tc;     // storage types: 0 complex128, 1 complex64
+  Map3 am, bn, cm, cn;
+  long long aks, bks;
+  Map3 ba, bb, bc;
+  double alpha_r;
+  double beta_r;
+  int beta_zero;
+  int tri;            // as GemmDesc::tri
+  int batch_fastest;  // as GemmDesc::batch_fastest
+  int group;          // as GemmDesc::group
+  int kchunk;         // fp32 accumulation length before the fp64 sum (multiple of 32)
+  int tag;            // KC_POL_CONTRACT or KC_SE_CONTRACT
+  int cfg;            // tile configuration (see bsgemm_launch)
+  Udiv q_tiles_m, q_tiles, q_batch;
+};
+
+static inline SplitDesc split_desc() {
+  SplitDesc d{};
+  d.am = d.bn = d.cm = d.cn = aff(0);
+  d.ba = d.bb = d.bc = aff(0);
+  d.alpha_r = 1.0;
+  d.beta_zero = 1;
+  d.batch = 1;
+  d.kchunk = 512;
+  d.cfg = -1;
   return d;
 }
 
@@ -104,6 +143,7 @@ struct DysonArgs {
 };
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st);
+hipError_t bsgemm_launch(const SplitDesc& d, hipStream_t st);
 hipError_t dyson_launch(const DysonArgs& a, int nw, hipStream_t st);
 hipError_t sum_launch(const double* x, long long n, double scale, double* out, hipStream_t st);
 hipError_t trace_launch(const double2* g, const double2* S, int n, int nk, double* part,

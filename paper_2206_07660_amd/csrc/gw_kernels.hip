@@ -81,6 +81,67 @@ __device__ __forceinline__ long long batch_off(const Map3& m, const int* tab, co
   return o;
 }
 
+// Output tile (tm, tn) and batch entry bt of this workgroup.  XCD-aware
+// order: the dispatcher deals workgroup ids round-robin over the 8 XCDs, so
+// id w runs on XCD w % 8.  Each XCD gets a contiguous range of logical ids,
+// so that the tiles of one batch entry (which share operand rows and
+// columns) meet in the same L2.  With d.tri only the tiles on or above the
+// diagonal are enumerated, row by row.  With d.batch_fastest = 1 the batch
+// shares an operand (e.g. one V slab for every tau): consecutive ids walk the
+// batch and keep that operand's tile in L2; = 2 does the same for groups of
+// d.group tiles.
+struct TilePos {
+  int tm, tn;
+  unsigned bt;
+};
+
+template <class D>
+__device__ __forceinline__ TilePos tile_pos(const D& d, int TM, int TN) {
+  const int tiles_m = (d.M + TM - 1) / TM;
+  const unsigned tiles = d.tri ? (unsigned)tiles_m * (unsigned)(tiles_m + 1) / 2u
+                               : (unsigned)tiles_m * (unsigned)((d.N + TN - 1) / TN);
+  const unsigned total = gridDim.x;
+  const unsigned w = blockIdx.x;
+  const unsigned xcd = w % 8u, slot = w / 8u, per = total / 8u, rem = total % 8u;
+  const unsigned logical = xcd < rem ? xcd * (per + 1u) + slot : rem * (per + 1u) + (xcd - rem) * per + slot;
+  const unsigned nbatch = (unsigned)d.batch;
+  unsigned tile, bt;
+  if (d.batch_fastest == 2) {
+    // groups of d.group consecutive tiles (the last one may be shorter): a
+    // group walks the batch, each batch entry its tiles, so the operand the
+    // batch shares stays in L2 for the group while each entry's own operand
+    // is fetched once per group
+    const unsigned G = (unsigned)d.group, span = G * nbatch, full = tiles / G;
+    const unsigned g = logical / span;
+    const unsigned gl = g < full ? G : tiles - full * G;
+    const unsigned rem = logical - g * span;
+    bt = rem / gl;
+    tile = g * G + (rem - bt * gl);
+  } else {
+    const unsigned lq = udiv(logical, d.batch_fastest ? d.q_batch : d.q_tiles);
+    const unsigned lr = logical - lq * (d.batch_fastest ? nbatch : tiles);
+    tile = d.batch_fastest ? lq : lr;
+    bt = d.batch_fastest ? lr : lq;
+  }
+  TilePos p;
+  if (d.tri) {
+    unsigned t = tile, r = 0, len = (unsigned)tiles_m;
+    while (t >= len) {
+      t -= len;
+      ++r;
+      --len;
+    }
+    p.tm = (int)r;
+    p.tn = (int)(r + t);
+  } else {
+    const unsigned tn_ = udiv(tile, d.q_tiles_m);
+    p.tm = (int)(tile - tn_ * (unsigned)tiles_m);
+    p.tn = (int)tn_;
+  }
+  p.bt = bt;
+  return p;
+}
+
 // ---------------------------------------------------------------------------
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b], complex.
 // Waves: WM x WN tile the output, WK split the K loop (reduced through LDS).
@@ -103,6 +164,16 @@ template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { ret
 template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) {
   return float2{(float)v.x, (float)v.y};
 }
+
+// bf16 pairs (round to nearest even) for the split-bf16 contractions:
+// element 0 in the low half, as in memory.
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf16(float a, float b) {
+  const bf2v v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(unsigned, v);
+}
+__device__ __forceinline__ float bf16_low(unsigned p) { return __builtin_bit_cast(float, p << 16); }
+__device__ __forceinline__ float bf16_high(unsigned p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
 
 template <bool F32> struct Mfma;
 template <> struct Mfma<false> {
@@ -183,40 +254,9 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   // the wave index is uniform within a wave; saying so keeps the K loop scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WM, wn = (wave / WM) % WN, wk = wave / (WM * WN);
-  // XCD-aware order: the dispatcher deals workgroup ids round-robin over the
-  // 8 XCDs, so id w runs on XCD w % 8.  Give each XCD a contiguous range of
-  // logical ids, so that the tiles of one batch entry (which share operand
-  // rows and columns) meet in the same L2.
-  const int tiles_m = (d.M + TM - 1) / TM;
-  // with d.tri, the tiles on or above the diagonal, row by row
-  const unsigned tiles = d.tri ? (unsigned)tiles_m * (unsigned)(tiles_m + 1) / 2u
-                               : (unsigned)tiles_m * (unsigned)((d.N + TN - 1) / TN);
-  const unsigned total = gridDim.x;
-  const unsigned w = blockIdx.x;
-  const unsigned xcd = w % 8u, slot = w / 8u, per = total / 8u, rem = total % 8u;
-  const unsigned logical = xcd < rem ? xcd * (per + 1u) + slot : rem * (per + 1u) + (xcd - rem) * per + slot;
-  // batch_fastest: the batch shares an operand (e.g. one V slab for every
-  // tau), so consecutive ids walk the batch and keep that operand's tile in L2.
-  const unsigned nbatch = (unsigned)d.batch;
-  const unsigned lq = udiv(logical, d.batch_fastest ? d.q_batch : d.q_tiles);
-  const unsigned lr = logical - lq * (d.batch_fastest ? nbatch : tiles);
-  const unsigned tile = d.batch_fastest ? lq : lr;
-  int tm, tn;
-  if (d.tri) {
-    unsigned t = tile, r = 0, len = (unsigned)tiles_m;
-    while (t >= len) {
-      t -= len;
-      ++r;
-      --len;
-    }
-    tm = (int)r;
-    tn = (int)(r + t);
-  } else {
-    const unsigned tn_ = udiv(tile, d.q_tiles_m);
-    tm = (int)(tile - tn_ * (unsigned)tiles_m);
-    tn = (int)tn_;
-  }
-  const unsigned bt = d.batch_fastest ? lr : lq;
+  const TilePos tp = tile_pos(d, TM, TN);
+  const int tm = tp.tm, tn = tp.tn;
+  const unsigned bt = tp.bt;
 
   const TA* A = (const TA*)d.A + batch_off(d.ba, d.tab, d.q_tmod, d.tsA, bt);
   const TB* B = (const TB*)d.B + batch_off(d.bb, d.tab, d.q_tmod, d.tsB, bt);
@@ -718,6 +758,353 @@ hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
     case KC_HF: return launch_tag<KC_HF>(d, st);
     default: return launch_tag<0>(d, st);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Split-bf16 complex GEMM (bf16x3), the mixed-precision form of the two large
+// contractions:  C[b](m, n) = alpha * sum_k A[b](m, k) B[b](n, k) + beta C[b](m, n)
+// with A(m, k) = A[ba(b) + am(m) + k aks] and B(n, k) = B[bb(b) + bn(n) + k bks],
+// complex128 or complex64 in memory.  Each K-step of 32 brings the A and B
+// tiles into LDS, splitting every real part x on the way into hi = bf16(x)
+// and lo = bf16(x - hi) (16 significant bits together); each real product is
+// then a_hi b_hi + a_hi b_lo + a_lo b_hi on v_mfma_f32_16x16x32_bf16 (the
+// dropped a_lo b_lo and the split residuals are near 2^-17 |a b|).  The
+// Im(a) Im(b) part of Re(a b) accumulates on its own and is subtracted at the
+// end of each chunk, so the loop has no sign flips.
+// LDS row of a tile: 32 k as four planes [hi(re)][hi(im)][lo(re)][lo(im)] of
+// 8 x 4 bf16 (64 bytes each), rows kRowB bytes apart (16 bytes of padding
+// spread the rows of one fragment read over the banks); two stages, so the
+// splits of step s + 1 overlap the MFMAs of step s, while the global loads
+// run three steps ahead (two register slots).
+// Loader: each thread owns chunks of 8 consecutive k of one row; with aks = 1
+// four threads read a row's 32 k (k-contiguous operands), otherwise
+// consecutive threads take consecutive rows (operands contiguous along the
+// rows, e.g. V with k = Q').  k >= K reads zeros.
+// MFMA operand layout: lane l holds row l % 16 and k = 8 (l / 16) .. +7 of A
+// (column l % 16, same k, of B); the result holds column l % 16 and rows
+// 4 (l / 16) .. +3.  Waves: WM x WN tile the output, each BM x BN blocks.
+// SUMS: fp32 accumulation inside chunks of d.kchunk k, each chunk added into
+// fp64; without them (K <= kchunk) one fp32 chunk.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+static constexpr int kRowB = 272;
+
+template <class T> struct Chunk;
+template <> struct Chunk<float2> { float2 v[8]; };
+template <> struct Chunk<double2> { double2 v[8]; };
+
+// loads 8 consecutive k (stride ks elements, 1 if CONTIG) from p; k >= K
+// gives zeros
+template <bool CONTIG, class T>
+__device__ __forceinline__ void load_chunk(Chunk<T>& c, const T* p, long long ks, int k0, int K) {
+  if (k0 + 8 <= K) {
+    if constexpr (CONTIG) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) c.v[e] = p[k0 + e];
+    } else {
+      // byte stride as a wave-uniform 32-bit value: the eight addresses are
+      // scalar offsets from one per-lane pointer
+      const unsigned sb = __builtin_amdgcn_readfirstlane((unsigned)(ks * (long long)sizeof(T)));
+      const char* q = (const char*)(p + (long long)k0 * ks);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) c.v[e] = *(const T*)(q + (unsigned)e * sb);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + e;
+      const T z{0, 0};
+      c.v[e] = k < K ? p[(long long)k * ks] : z;
+    }
+  }
+}
+
+// split 8 complex values and write the four planes of one LDS chunk
+template <class T>
+__device__ __forceinline__ void put_chunk(const Chunk<T>& c, unsigned char* row, int kgc) {
+  float re[8], im[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    re[e] = (float)c.v[e].x;
+    im[e] = (float)c.v[e].y;
+  }
+  uint4 hr, hi, lr, li;
+  unsigned* phr = (unsigned*)&hr;
+  unsigned* phi = (unsigned*)&hi;
+  unsigned* plr = (unsigned*)&lr;
+  unsigned* pli = (unsigned*)&li;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    phr[i] = pack_bf16(re[2 * i], re[2 * i + 1]);
+    phi[i] = pack_bf16(im[2 * i], im[2 * i + 1]);
+    plr[i] = pack_bf16(re[2 * i] - bf16_low(phr[i]), re[2 * i + 1] - bf16_high(phr[i]));
+    pli[i] = pack_bf16(im[2 * i] - bf16_low(phi[i]), im[2 * i + 1] - bf16_high(phi[i]));
+  }
+  uint4* q = (uint4*)(row + 16 * kgc);
+  q[0] = hr;
+  q[4] = hi;
+  q[8] = lr;
+  q[12] = li;
+}
+
+template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
+          int PF>
+__global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
+  constexpr int NT = 64 * WM * WN, TM = WM * BM * 16, TN = WN * BN * 16;
+  constexpr int CA = TM * 4 / NT, CB = TN * 4 / NT;   // loader chunks per thread
+  static_assert(CA >= 1 && CB >= 1 && CA * NT == TM * 4 && CB * NT == TN * 4, "loader split");
+  constexpr int STAGE = (TM + TN) * kRowB;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % WM, wn = wave / WM;
+  const TilePos tp = tile_pos(d, TM, TN);
+  const TA* A = (const TA*)d.A + map3(d.ba, tp.bt);
+  const TB* B = (const TB*)d.B + map3(d.bb, tp.bt);
+  const int tm0 = tp.tm * TM, tn0 = tp.tn * TN;
+
+  // loader rows (clamped to the last row: their outputs are dropped); AK1,
+  // BK1: the operand's K stride is 1
+  constexpr bool acontig = AK1, bcontig = BK1;
+  const TA* pa[CA];
+  const TB* pb[CB];
+  int ra[CA], ka[CA], rb[CB], kb[CB];
+#pragma unroll
+  for (int u = 0; u < CA; ++u) {
+    const int c = tid + u * NT;
+    ra[u] = acontig ? c >> 2 : c % TM;
+    ka[u] = acontig ? c & 3 : c / TM;
+    pa[u] = A + map3(d.am, (unsigned)min(tm0 + ra[u], d.M - 1));
+  }
+#pragma unroll
+  for (int u = 0; u < CB; ++u) {
+    const int c = tid + u * NT;
+    rb[u] = bcontig ? c >> 2 : c % TN;
+    kb[u] = bcontig ? c & 3 : c / TN;
+    pb[u] = B + map3(d.bn, (unsigned)min(tn0 + rb[u], d.N - 1));
+  }
+  // PF (1 or 2) register slots of loaded chunks: the loads of step s + 1 + PF
+  // are issued during step s (with PF = 2 they are in flight during the
+  // MFMAs of two steps)
+  Chunk<TA> ca[PF][CA];
+  Chunk<TB> cb[PF][CB];
+  auto fetch = [&](int s, auto slot) {
+    constexpr int sl = decltype(slot)::value;
+#pragma unroll
+    for (int u = 0; u < CA; ++u) load_chunk<AK1>(ca[sl][u], pa[u], d.aks, 32 * s + 8 * ka[u], d.K);
+#pragma unroll
+    for (int u = 0; u < CB; ++u) load_chunk<BK1>(cb[sl][u], pb[u], d.bks, 32 * s + 8 * kb[u], d.K);
+  };
+  auto stash = [&](auto slot, int stage) {
+    constexpr int sl = decltype(slot)::value;
+    unsigned char* base = lds + stage * STAGE;
+#pragma unroll
+    for (int u = 0; u < CA; ++u) put_chunk(ca[sl][u], base + ra[u] * kRowB, ka[u]);
+#pragma unroll
+    for (int u = 0; u < CB; ++u) put_chunk(cb[sl][u], base + (TM + rb[u]) * kRowB, kb[u]);
+  };
+
+  f4 accR[BM][BN], accN[BM][BN], accI[BM][BN];
+  double sumR[SUMS ? BM : 1][SUMS ? BN : 1][4], sumI[SUMS ? BM : 1][SUMS ? BN : 1][4];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) accR[i][j] = accN[i][j] = accI[i][j] = f4{0, 0, 0, 0};
+  if constexpr (SUMS) {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sumR[i][j][r] = sumI[i][j][r] = 0.0;
+  }
+  auto promote = [&]() {
+    if constexpr (SUMS) {
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            sumR[i][j][r] += (double)accR[i][j][r] - (double)accN[i][j][r];
+            sumI[i][j][r] += (double)accI[i][j][r];
+          }
+          accR[i][j] = accN[i][j] = accI[i][j] = f4{0, 0, 0, 0};
+        }
+    }
+  };
+  const int r16 = lane & 15, kg = lane >> 4;
+  auto bf = [](const uint4& v) { return __builtin_bit_cast(bf8v, v); };
+  // one K-step from LDS stage `stage`: planes 0 hi(re), 1 hi(im), 2 lo(re),
+  // 3 lo(im).  Terms (hi, hi), (hi, lo), (lo, hi) in three phases, each
+  // reading only the planes it adds.
+  auto rd = [&](const unsigned char* base, int row0, int p) {
+    return *(const uint4*)(base + (row0 + r16) * kRowB + 16 * kg + 64 * p);
+  };
+  auto terms = [&](const uint4 (&ar)[BM], const uint4 (&ai)[BM], const uint4 (&br)[BN], const uint4 (&bi)[BN]) {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(ar[i]), bf(br[j]), accR[i][j], 0, 0, 0);
+        accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(ar[i]), bf(bi[j]), accI[i][j], 0, 0, 0);
+        accN[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(ai[i]), bf(bi[j]), accN[i][j], 0, 0, 0);
+      }
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j)
+        accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf(ai[i]), bf(br[j]), accI[i][j], 0, 0, 0);
+  };
+  auto compute = [&](int stage) {
+    const unsigned char* base = lds + stage * STAGE;
+    const int ra0 = wm * BM * 16, rb0 = TM + wn * BN * 16;
+    uint4 ahr[BM], ahi[BM], bhr[BN], bhi[BN];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+      ahr[i] = rd(base, ra0 + 16 * i, 0);
+      ahi[i] = rd(base, ra0 + 16 * i, 1);
+    }
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      bhr[j] = rd(base, rb0 + 16 * j, 0);
+      bhi[j] = rd(base, rb0 + 16 * j, 1);
+    }
+    terms(ahr, ahi, bhr, bhi);
+    {
+      uint4 blr[BN], bli[BN];
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        blr[j] = rd(base, rb0 + 16 * j, 2);
+        bli[j] = rd(base, rb0 + 16 * j, 3);
+      }
+      terms(ahr, ahi, blr, bli);
+    }
+    uint4 alr[BM], ali[BM];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+      alr[i] = rd(base, ra0 + 16 * i, 2);
+      ali[i] = rd(base, ra0 + 16 * i, 3);
+    }
+    terms(alr, ali, bhr, bhi);
+  };
+
+  // step t's chunks live in register slot t % PF and LDS stage t % 2
+  const int nsteps = (d.K + 31) / 32;
+  const int cper = d.kchunk / 32;
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, PF - 1>;
+  if constexpr (PF == 1) {
+    fetch(0, S0{});
+    stash(S0{}, 0);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+      if (s + 1 < nsteps) fetch(s + 1, S0{});
+      compute(s & 1);
+      if (s + 1 < nsteps) stash(S0{}, (s + 1) & 1);
+      if ((s + 1) % cper == 0) promote();
+      __syncthreads();
+    }
+  } else {
+    fetch(0, S0{});
+    stash(S0{}, 0);
+    if (nsteps > 1) fetch(1, S1{});
+    if (nsteps > 2) fetch(2, S0{});
+    __syncthreads();
+    auto step = [&](int s, auto next) {           // next: slot of step s + 1
+      compute(s & 1);
+      if (s + 1 < nsteps) stash(next, (s + 1) & 1);
+      if (s + 3 < nsteps) fetch(s + 3, next);
+      if ((s + 1) % cper == 0) promote();
+      __syncthreads();
+    };
+    for (int s = 0; s < nsteps; s += 2) {
+      step(s, S1{});
+      if (s + 1 < nsteps) step(s + 1, S0{});
+    }
+  }
+  promote();
+
+  // epilogue: fp32 MFMA result layout, rows 4 (lane / 16) + r, column lane % 16
+  auto res = [&](int i, int j, int r, bool im) -> double {
+    if constexpr (SUMS) return im ? sumI[i][j][r] : sumR[i][j][r];
+    else return im ? (double)accI[i][j][r] : (double)accR[i][j][r] - (double)accN[i][j][r];
+  };
+  TC* C = (TC*)d.C + map3(d.bc, tp.bt);
+  const int m0 = tm0 + wm * BM * 16, n0 = tn0 + wn * BN * 16;
+  long long roff[BM][4];
+  bool rok[BM][4];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + i * 16 + 4 * kg + r;
+      rok[i][r] = m < d.M;
+      roff[i][r] = rok[i][r] ? map3(d.cm, m) : 0;
+    }
+#pragma unroll
+  for (int j = 0; j < BN; ++j) {
+    const int n = n0 + j * 16 + r16;
+    if (n >= d.N) continue;
+    const long long con = map3(d.cn, n);
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (!rok[i][r]) continue;
+        const long long o = roff[i][r] + con;
+        double2 v{d.alpha_r * res(i, j, r, false), d.alpha_r * res(i, j, r, true)};
+        if (!d.beta_zero) {
+          const double2 c = to_d2(C[o]);
+          v.x += d.beta_r * c.x;
+          v.y += d.beta_r * c.y;
+        }
+        C[o] = from_d2<TC>(v);
+      }
+  }
+}
+
+template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
+          int PF>
+static hipError_t bs_cfg(const SplitDesc& d0, hipStream_t st) {
+  constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
+  const long long tm_ = (d0.M + TM - 1) / TM;
+  if (d0.tri && (d0.M != d0.N || TM != TN)) return hipErrorInvalidValue;
+  if (!SUMS && d0.K > d0.kchunk) return hipErrorInvalidValue;
+  if (d0.batch_fastest == 2 && d0.group <= 0) return hipErrorInvalidValue;
+  const long long tiles = d0.tri ? tm_ * (tm_ + 1) / 2 : tm_ * ((d0.N + TN - 1) / TN);
+  if (tiles * (long long)d0.batch > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  SplitDesc d = d0;
+  d.q_tiles_m = udiv_make((unsigned)tm_);
+  d.q_tiles = udiv_make((unsigned)tiles);
+  d.q_batch = udiv_make((unsigned)d.batch);
+  if ((d0.aks == 1) != AK1 || (d0.bks == 1) != BK1) return hipErrorInvalidValue;
+  bsgemm_k<WM, WN, BM, BN, TAG, TA, TB, TC, SUMS, AK1, BK1, PF><<<dim3((unsigned)(tiles * d.batch)), 64 * WM * WN, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+// Tile configurations (d.cfg < 0: the default of the role).  Polarization
+// (complex64 operands, long K with fp64 chunk sums, square tiles for the
+// Hermitian mode): 64x64 on 4 waves, loads three steps ahead.  Self-energy
+// P~ V (complex64 P~ and V, K = naux <= kchunk; loads one step ahead):
+// 0 128x128 on 8 waves (4 x 2 blocks each), 1 64x64 on 4 waves, 2 128x64 on
+// 4 waves (4 x 2).
+hipError_t bsgemm_launch(const SplitDesc& d, hipStream_t st) {
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+  if (d.K <= 0 || d.kchunk <= 0 || d.kchunk % 32) return hipErrorInvalidValue;
+  // the polarization's operands have K contiguous; the self-energy's V has
+  // K = Q' with stride n2
+  if (d.tag == KC_POL_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 0)
+    return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, 2>(d, st);
+  if (d.tag == KC_SE_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 1) {
+    if (d.K > d.kchunk) return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false, 1>(d, st);
+    switch (d.cfg) {
+      case 1: return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, 1>(d, st);
+      case 2: return bs_cfg<2, 2, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, 1>(d, st);
+      default: return bs_cfg<2, 4, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, 1>(d, st);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

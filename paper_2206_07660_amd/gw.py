@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libgw.so")
 (GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPACE, GW_ERR_STATE,
  GW_ERR_NONFINITE) = range(8)
 GW_FERMION, GW_BOSON = 0, 1
-GW_PREC_FP64, GW_PREC_FP32 = 0, 1
+GW_PREC_FP64, GW_PREC_FP32, GW_PREC_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": GW_PREC_FP64, "fp32": GW_PREC_FP32, "bf16x3": GW_PREC_BF16X3}
 (GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF, GW_OP_DYSON_JVP, GW_OP_SIGMA,
  GW_OP_THERMO) = range(7)
 KCLASS = dict(other=0, pol_contract=1, pol_producer=2, se_contract=3, se_producer=4,
@@ -194,8 +195,8 @@ class Context:
         (pass None) with nw_f = ntau and nw_b = ntau + 1."""
         import torch
         L = load()
-        if precision not in ("fp64", "fp32"):
-            raise ValueError("precision is 'fp64' or 'fp32'")
+        if precision not in PRECISIONS:
+            raise ValueError("precision is one of " + ", ".join(repr(k) for k in PRECISIONS))
         self.precision = precision
         self.v_dtype = torch.complex128 if precision == "fp64" else torch.complex64
         self.mesh = tuple(int(m) for m in mesh)
@@ -212,7 +213,7 @@ class Context:
         else:
             self.nw_f, self.nw_b = len(grids["nF"]), len(grids["nB"])
         d = Dims((ctypes.c_int * 3)(*self.mesh), self.nao, self.naux, self.ntau, self.nw_f,
-                 self.nw_b, self.ns, GW_PREC_FP64 if precision == "fp64" else GW_PREC_FP32,
+                 self.nw_b, self.ns, PRECISIONS[precision],
                  self.beta)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()

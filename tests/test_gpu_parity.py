@@ -429,7 +429,7 @@ def test_workspace_too_small(small):
 
 
 def test_descriptor_bounds_whole_path(small, monkeypatch):
-    """With GW_DEBUG_BOUNDS=1 every GEMM descriptor of the forward chain (both
+    """With GW_DEBUG_BOUNDS=1 every GEMM descriptor of the forward chain (all
     precisions, Hermitian mode on and off), the transforms and the derivative
     calls is proven on the host to stay inside its operands; a failure would
     surface as a GwError."""
@@ -438,7 +438,7 @@ def test_descriptor_bounds_whole_path(small, monkeypatch):
     from paper_2206_07660_amd.scgw import GWPath
     monkeypatch.setenv("GW_DEBUG_BOUNDS", "1")
     wl = small["wl"]
-    for precision in ("fp64", "fp32"):
+    for precision in ("fp64", "fp32", "bf16x3"):
         c = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=7,
                        precision=precision)
         try:

@@ -43,11 +43,14 @@ def _pair(wl, q0, nq, precision, herm):
     return a, b, ref
 
 
-@pytest.mark.parametrize("precision,herm", [("fp64", False), ("fp64", True), ("fp32", False)])
+@pytest.mark.parametrize("precision,herm", [("fp64", False), ("fp64", True), ("fp32", False),
+                                            ("bf16x3", True)])
 def test_noalloc_matches_workspace_form_twice(precision, herm):
     big = inp.small_workload(mesh=(2, 2, 2), nao=10, naux=70, ntau=20, beta=20.0, seed=81)
     small = inp.small_workload(mesh=(2, 1, 1), nao=6, naux=30, ntau=12, beta=10.0, seed=82)
-    tol = 1e-13 if precision == "fp64" else 1e-6
+    # vs the oracle, relative to the largest entry: rounding of fp64; of
+    # complex64 operands; of bf16x3 products (near 2^-17 each, 4x margin)
+    tol = {"fp64": 1e-13, "fp32": 1e-6, "bf16x3": 1e-4}[precision]
     for wl, q0, nq in ((big, 1, 5), (small, 1, 1)):          # the second call is smaller
         a, b, ref = _pair(wl, q0, nq, precision, herm)
         assert np.isfinite(b).all()
