@@ -407,10 +407,14 @@ gw_status gw_mix(gw_ctx* ctx, long long n, double alpha, const gw_z* X_new, gw_z
                  double* maxdiff);
 
 /* ---- Derivatives of G -> (Sigma_inf, Sigma~) ----
- * The JVP calls (gw_polarization2, gw_screened_W_lin, gw_transform_adjoint,
- * gw_dyson_jvp, with gw_hf and gw_self_energy, which are linear in G and in
- * P~) run in either precision; the VJP calls that read V (gw_self_energy_vjp,
- * gw_polarization_vjp, gw_hf_vjp) need a GW_PREC_FP64 context.
+ * All run in every precision.  The JVP calls (gw_polarization2,
+ * gw_screened_W_lin, gw_transform_adjoint, gw_dyson_jvp, with gw_hf and
+ * gw_self_energy, which are linear in G and in P~) follow the forward
+ * precision; in the complex64 modes the VJP calls that read V
+ * (gw_self_energy_vjp, gw_polarization_vjp; V is gw_c there) run their
+ * products as complex fp32 MFMA GEMMs with complex64 intermediates and fp64
+ * sums of 512-term chunks, and gw_hf_vjp reads the complex64 V in fp64
+ * arithmetic; the cotangents and results are complex128.
  * The map is holomorphic in G, so a vector-Jacobian product (VJP) applies the
  * conjugate-transposed Jacobian to the cotangent; for a real loss L of the
  * outputs this is the gradient dL/dRe + i dL/dIm (torch autograd convention).
@@ -441,18 +445,18 @@ gw_status gw_transform_adjoint(gw_ctx* ctx, int stat, int inverse, const gw_z* X
 /* VJP of Eq. tilde_sigma2 for q = q0 .. q0+nq-1 with cotangent Sig_bar
  * [tau][k][i][j]: G_bar += the G part (accumulated), Pt_bar[q-q0][tau]
  * receives the P~ part (overwritten).                                        */
-gw_status gw_self_energy_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* Pt_tau,
+gw_status gw_self_energy_vjp(gw_ctx* ctx, const void* V, const gw_z* G_tau, const gw_z* Pt_tau,
                              const gw_z* Sig_bar, int q0, int nq, gw_z* G_bar, gw_z* Pt_bar);
 
 /* VJP of Eq. tilde_P0_tau (both G slots) with cotangent P0_bar[q-q0][tau]:
  * G_bar += (accumulated).                                                    */
-gw_status gw_polarization_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* P0_bar,
+gw_status gw_polarization_vjp(gw_ctx* ctx, const void* V, const gw_z* G_tau, const gw_z* P0_bar,
                               int q0, int nq, gw_z* G_bar);
 
 /* VJP of G -> gamma = -G(beta^-) -> Sigma_inf = J + K (Eqs. HF_J, HF_K) with
  * cotangent Sinf_bar [k][i][j]: G_bar += (accumulated).  The JVP is gw_hf
  * itself, which is linear in G.                                             */
-gw_status gw_hf_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* Sinf_bar, gw_z* G_bar);
+gw_status gw_hf_vjp(gw_ctx* ctx, const void* V, const gw_z* Sinf_bar, gw_z* G_bar);
 
 /* JVP of the Dyson step with the electron count held fixed (Eq. Dyson,
  * Sec. IV.A): for G(i w) at the current mu and a change of the self-energy
@@ -479,11 +483,11 @@ gw_status gw_dyson_jvp(gw_ctx* ctx, const gw_z* S, const gw_z* G_iw, const gw_z*
  * the Hermitian mode of gw_set_hermitian), so nothing of size Nk naux^2 is
  * held.  The JVP uses GW_HERM_TWO_SLOT when set (dG Hermitian like G).
  * Outputs are overwritten: dSig_inf [k][i][j], dSig_tau and G_bar
- * [tau][k][i][j].  Workspace GW_OP_SIGMA.  The JVP runs in either precision,
- * the VJP needs a GW_PREC_FP64 context.                                     */
+ * [tau][k][i][j].  Workspace GW_OP_SIGMA.  Both run in every precision
+ * (V complex128 or, in the complex64 modes, gw_c).                         */
 gw_status gw_sigma_jvp(gw_ctx* ctx, const void* V, const gw_z* G_tau, const gw_z* Pt_tau,
                        const gw_z* Pt_iw, const gw_z* dG_tau, gw_z* dSig_inf, gw_z* dSig_tau);
-gw_status gw_sigma_vjp(gw_ctx* ctx, const gw_z* V, const gw_z* G_tau, const gw_z* Pt_tau,
+gw_status gw_sigma_vjp(gw_ctx* ctx, const void* V, const gw_z* G_tau, const gw_z* Pt_tau,
                        const gw_z* Pt_iw, const gw_z* Sinf_bar, const gw_z* Stau_bar, gw_z* G_bar);
 
 /* Vector operations of the Newton-Krylov solver: Y = a X + b Y for complex

@@ -1437,13 +1437,6 @@ static gw_status need_grids(gw_ctx* c) {
   return GW_OK;
 }
 
-static gw_status need_fp64(gw_ctx* c) {
-  if (!c) return GW_ERR_ARG;
-  if (!ready(c)) return fail(c, GW_ERR_STATE, "grids not built (gw_build_grids or gw_set_grids)");
-  if (c->d.precision != GW_PREC_FP64) return fail(c, GW_ERR_ARG, "derivatives need a GW_PREC_FP64 context");
-  return GW_OK;
-}
-
 gw_status gw_screened_W_lin(gw_ctx* c, const gw_z* Pt, const gw_z* X, int nq, int adjoint, gw_z* Y) {
   gw_status s = need_grids(c);
   if (s != GW_OK) return s;
@@ -1506,9 +1499,22 @@ gw_status gw_transform_adjoint(gw_ctx* c, int stat, int inverse, const gw_z* Xin
   return run(c, g, Ext{0, (long long)rows * inner}, Ext{0, batch * inner * R}, Ext{0, batch * rows * R});
 }
 
-gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt,
+// The VJP contractions in every precision: fp64, or in the complex64 modes
+// V complex64, complex64 intermediates, fp32 MFMA (operands rounded on load)
+// with fp64 sums of 512-term chunks for the long contractions, outputs fp64.
+struct VjpMode {
+  int t;        // storage type of V and of the intermediates
+  size_t ez;    // their element size
+  int kchunk;
+};
+static VjpMode vjp_mode(const gw_ctx* c) {
+  const bool f32 = lowp(c);
+  return VjpMode{f32 ? 1 : 0, f32 ? (size_t)8 : (size_t)16, f32 ? kMixedChunk : 0};
+}
+
+gw_status gw_self_energy_vjp(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt,
                              const gw_z* Sbar, int q0, int nq, gw_z* Gbar, gw_z* Ptbar) {
-  gw_status s = need_fp64(c);
+  gw_status s = need_grids(c);
   if (s != GW_OK) return s;
   if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
   if (nq == 0) return GW_OK;
@@ -1518,10 +1524,12 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
     return fail(c, GW_ERR_WORKSPACE, "self-energy workspace too small");
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv, S = (long long)nk * sv;
-  double2* R0 = (double2*)c->ws;
-  double2* R1 = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
+  const VjpMode vm = vjp_mode(c);
+  const int t = vm.t;
+  char* R0 = (char*)c->ws;
+  char* R1 = (char*)c->ws + region_bytes(c, tc);
   for (int q = q0; q < q0 + nq; ++q) {
-    const gw_z* Aq = V + (size_t)q * nk * sv;
+    const char* Aq = (const char*)V + (size_t)q * nk * sv * vm.ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {
       const int tcur = std::min(tc, nt - t0);
       const gw_z* Ptq = Pt + ((long long)(q - q0) * nt + t0) * naux * naux;
@@ -1532,6 +1540,7 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
       g.am = aff(naux); g.ak = aff(1); g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
       g.cm = aff((long long)nk * n2); g.cn = aff(1);
       g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
+      g.ta = 0; g.tb = g.tc = t; g.f32 = t;
       g.batch_fastest = 1;
       g.tag = KC_SE_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
@@ -1543,6 +1552,7 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
       g.cm = aff(nao); g.cn = two(nao, 1, S);
       g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;
+      g.ta = g.tc = t; g.tb = 0; g.f32 = t;
       g.tag = KC_SE_PRODUCER;
       if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
       // Gbar[t][kk][a][b] += -(1/nk) sum_{Q,j} L'[tl][kk][Q][a][j] conj(Vt[tl][Q][kk][b][j])
@@ -1554,6 +1564,7 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
       g.cm = aff(nao); g.cn = aff(1);
       g.ba = two(nk, sv, S); g.bb = two(nk, n2, S); g.bc = two(nk, n2, (long long)nk * n2);
       g.alpha_r = -1.0 / nk; g.beta_zero = 0; g.beta_r = 1.0;
+      g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = vm.kchunk;
       g.tag = KC_SE_FINAL;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * nk * n2})) != GW_OK) return s;
       // R0 = Y[tl][kk][Q'][a][j] = sum_b G[t][kk][a][b] V[q][kk][Q'][b][j]
@@ -1564,6 +1575,7 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
       g.bk = aff(nao); g.bn = two(nao, 1, n2);
       g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
       g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
+      g.ta = 0; g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_SE_PRODUCER;
       if ((s = run(c, g, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
       // Ptbar[q][t][Q][Q'] = -(1/nk) sum_{kk,a,j} L'[tl][kk][Q][a][j] conj(Y[tl][kk][Q'][a][j])
@@ -1575,6 +1587,7 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
       g.cm = aff(naux); g.cn = aff(1);
       g.ba = aff(S); g.bb = aff(S); g.bc = aff((long long)naux * naux);
       g.alpha_r = -1.0 / nk;
+      g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = vm.kchunk;
       g.tag = KC_POL_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * naux * naux})) != GW_OK) return s;
     }
@@ -1582,9 +1595,9 @@ gw_status gw_self_energy_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z
   return GW_OK;
 }
 
-gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* P0bar, int q0,
+gw_status gw_polarization_vjp(gw_ctx* c, const void* V, const gw_z* G, const gw_z* P0bar, int q0,
                               int nq, gw_z* Gbar) {
-  gw_status s = need_fp64(c);
+  gw_status s = need_grids(c);
   if (s != GW_OK) return s;
   if (q0 < 0 || nq < 0 || q0 + nq > c->nk) return fail(c, GW_ERR_ARG, "q range outside the mesh");
   if (nq == 0) return GW_OK;
@@ -1595,10 +1608,12 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv, S = (long long)nk * sv;
   const double sc = -(double)c->d.ns / nk;
-  double2* R0 = (double2*)c->ws;
-  double2* R1 = (double2*)((char*)c->ws + align256((size_t)tc * S * 16));
+  const VjpMode vm = vjp_mode(c);
+  const int t = vm.t;
+  char* R0 = (char*)c->ws;
+  char* R1 = (char*)c->ws + region_bytes(c, tc);
   for (int q = q0; q < q0 + nq; ++q) {
-    const gw_z* Aq = V + (size_t)q * nk * sv;
+    const char* Aq = (const char*)V + (size_t)q * nk * sv * vm.ez;
     for (int t0 = 0; t0 < nt; t0 += tc) {
       const int tcur = std::min(tc, nt - t0);
       const gw_z* Pb = P0bar + ((long long)(q - q0) * nt + t0) * naux * naux;
@@ -1611,6 +1626,7 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
       g.bk = aff(nao); g.bn = two(nao, 1, n2);
       g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
       g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
+      g.ta = 0; g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_POL_PRODUCER;
       if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tc * S})) != GW_OK) return s;
       // R0 = U[tl][Q][k][e] = sum_Q' Pbar[Q][Q'] W[tl][k][Q'][e]
@@ -1620,6 +1636,7 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
       g.am = aff(naux); g.ak = aff(1); g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv);
       g.cm = aff((long long)nk * n2); g.cn = aff(1);
       g.ba = aff((long long)naux * naux); g.bb = aff(S); g.bc = aff(S);
+      g.ta = 0; g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_SE_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
       // Gbar[t0+tl][k+q][a][b] += sc sum_{Q,d} conj(V[q][k][Q][d][a]) U[tl][Q][k][d][b]
@@ -1632,6 +1649,7 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
       g.ba = two(nk, sv, 0); g.bb = two(nk, n2, S); g.bc = two(nk, 0, (long long)nk * n2);
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
       g.alpha_r = sc; g.beta_zero = 0; g.beta_r = 1.0;
+      g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = vm.kchunk;
       g.tag = KC_SE_FINAL;
       if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * nk * n2})) != GW_OK) return s;
       // --- mirrored slot: Gbar[nt-1-t][k] += sc sum_{Q',b} V[q][k][Q'][c][b] T[Q'][k][d][b]
@@ -1643,6 +1661,7 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
       g.cm = aff(nao); g.cn = two(nao, 1, S);
       g.ba = aff(sv); g.bb = aff(0); g.bc = aff(sv);
       g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsB = n2;
+      g.ta = g.tc = t; g.tb = 0; g.f32 = t;
       g.tag = KC_POL_PRODUCER;
       if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * S})) != GW_OK) return s;
       // R0 = T[tl][Q'][k][e] = sum_Q Pbar[Q][Q'] conj(X[tl][k][Q][e])
@@ -1652,6 +1671,7 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
       g.am = aff(1); g.ak = aff(naux); g.bk = aff(n2); g.bn = two((unsigned)n2, 1, sv); g.conjB = 1;
       g.cm = aff((long long)nk * n2); g.cn = aff(1);
       g.ba = aff((long long)naux * naux); g.bb = aff(S); g.bc = aff(S);
+      g.ta = 0; g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_SE_CONTRACT;
       if ((s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)tcur * S}, Ext{0, (long long)tcur * S})) != GW_OK) return s;
       // Gbar[nt-1-t0-tl][k][c][d] += sc sum_{Q',b} V[q][k][Q'][c][b] T[tl][Q'][k][d][b]
@@ -1663,6 +1683,7 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
       g.cm = aff(nao); g.cn = aff(1);
       g.ba = two(nk, sv, 0); g.bb = two(nk, n2, S); g.bc = two(nk, n2, -(long long)nk * n2);
       g.alpha_r = sc; g.beta_zero = 0; g.beta_r = 1.0;
+      g.ta = g.tb = t; g.tc = 0; g.f32 = t; g.kchunk = vm.kchunk;
       g.tag = KC_SE_FINAL;
       if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S}, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2})) != GW_OK) return s;
     }
@@ -1670,37 +1691,43 @@ gw_status gw_polarization_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_
   return GW_OK;
 }
 
-gw_status gw_hf_vjp(gw_ctx* c, const gw_z* V, const gw_z* Sbar, gw_z* Gbar) {
-  gw_status s = need_fp64(c);
+gw_status gw_hf_vjp(gw_ctx* c, const void* V, const gw_z* Sbar, gw_z* Gbar) {
+  gw_status s = need_grids(c);
   if (s != GW_OK) return s;
   if (!V || !Sbar || !Gbar) return fail(c, GW_ERR_ARG, "NULL array");
   if (!c->ws || c->ws_bytes < gw_workspace_bytes(c, GW_OP_HF, 1))
     return fail(c, GW_ERR_WORKSPACE, "HF workspace too small");
   const int nk = c->nk, nao = c->d.nao, naux = c->d.naux, nt = c->d.ntau;
   const long long n2 = c->n2, sv = c->sv;
+  // complex64 V is read in fp64 arithmetic, as in gw_hf
+  const int tv = lowp(c) ? 1 : 0;
+  const size_t ez = tv ? 8 : 16;
+  const char* Vd = (const char*)V;
   double2* T2 = (double2*)c->ws;
   double2* gb = (double2*)((char*)c->ws + align256((size_t)nk * sv * 16));
   double2* vb = (double2*)((char*)gb + align256((size_t)nk * n2 * 16));
   // vbar[Q] = sum_{k,e} conj(V[0][k][Q][e]) Sbar[k][e]
   GemmDesc g = gemm_desc();
-  g.A = V; g.B = Sbar; g.C = vb;
+  g.A = Vd; g.B = Sbar; g.C = vb;
   g.M = naux; g.N = 1; g.K = nk * (int)n2;
   g.am = aff(n2); g.ak = two((unsigned)n2, 1, sv); g.conjA = 1;
   g.bk = aff(1); g.bn = aff(0); g.cm = aff(1); g.cn = aff(0);
+  g.ta = tv;
   g.tag = KC_HF;
   if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)naux})) != GW_OK) return s;
   // gbar[k'][a][b] = (ns/nk) sum_Q conj(V[0][k'][Q][b][a]) vbar[Q]
   g = gemm_desc();
-  g.A = vb; g.B = V; g.C = gb;
+  g.A = vb; g.B = Vd; g.C = gb;
   g.M = 1; g.N = nk * (int)n2; g.K = naux;
   g.am = aff(0); g.ak = aff(1);
   g.bk = aff(n2); g.bn = three(nao, nao, nao, 1, sv); g.conjB = 1;
   g.cm = aff(0); g.cn = aff(1);
   g.alpha_r = (double)c->d.ns / nk;
+  g.tb = tv;
   g.tag = KC_HF;
   if ((s = run(c, g, Ext{0, (long long)naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
   for (int q = 0; q < nk; ++q) {
-    const gw_z* Aq = V + (size_t)q * nk * sv;
+    const char* Aq = Vd + (size_t)q * nk * sv * ez;
     // T2[k][Q][b][i] = sum_j V[q][k][Q][j][b] Sbar[k][i][j]
     g = gemm_desc();
     g.A = Aq; g.B = Sbar; g.C = T2;
@@ -1708,6 +1735,7 @@ gw_status gw_hf_vjp(gw_ctx* c, const gw_z* V, const gw_z* Sbar, gw_z* Gbar) {
     g.am = two(nao, 1, n2); g.ak = aff(nao); g.bk = aff(1); g.bn = aff(nao);
     g.cm = aff(nao); g.cn = aff(1);
     g.ba = aff(sv); g.bb = aff(n2); g.bc = aff(sv);
+    g.ta = tv;
     g.tag = KC_HF;
     if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2}, Ext{0, (long long)nk * sv})) != GW_OK) return s;
     // gbar[k+q][a][b] += -(1/nk) sum_{Q,i} conj(V[q][k][Q][i][a]) T2[k][Q][b][i]
@@ -1720,6 +1748,7 @@ gw_status gw_hf_vjp(gw_ctx* c, const gw_z* V, const gw_z* Sbar, gw_z* Gbar) {
     g.ba = aff(sv); g.bb = aff(sv); g.bc = aff(0);
     g.tab = c->dplus + (size_t)q * nk; g.tmod = nk; g.tsC = n2;
     g.alpha_r = -1.0 / nk; g.beta_zero = 0; g.beta_r = 1.0;
+    g.ta = tv;
     g.tag = KC_HF;
     if ((s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * sv}, Ext{0, (long long)nk * n2})) != GW_OK) return s;
   }
@@ -1997,9 +2026,9 @@ gw_status gw_sigma_jvp(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt_t
   return GW_OK;
 }
 
-gw_status gw_sigma_vjp(gw_ctx* c, const gw_z* V, const gw_z* G, const gw_z* Pt_tau, const gw_z* Pt_iw,
+gw_status gw_sigma_vjp(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt_tau, const gw_z* Pt_iw,
                        const gw_z* Sinf_bar, const gw_z* Stau_bar, gw_z* G_bar) {
-  gw_status s = need_fp64(c);
+  gw_status s = need_grids(c);
   if (s != GW_OK) return s;
   bool stored = false;
   if ((s = deriv_args(c, V, G, Pt_tau, Pt_iw, &stored)) != GW_OK) return s;

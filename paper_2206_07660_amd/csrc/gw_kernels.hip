@@ -735,6 +735,9 @@ static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
   }
   if constexpr (TAG == KC_POL_PRODUCER || TAG == KC_SE_PRODUCER) {
     if (code == (8 | 1 | 2 | 4)) return launch_typed<TAG, float2, float2, float2, true>(d, st);
+    // mixed-precision VJP: complex64 V times a complex128 G or cotangent
+    if (code == (8 | 1 | 4)) return launch_typed<TAG, float2, double2, float2, true>(d, st);
+    if (code == (8 | 2 | 4)) return launch_typed<TAG, double2, float2, float2, true>(d, st);
   }
   if constexpr (TAG == KC_POL_CONTRACT || TAG == KC_SE_FINAL) {
     if (code == (8 | 1 | 2)) return launch_typed<TAG, float2, float2, double2, true>(d, st);

@@ -462,7 +462,7 @@ def gw_sigma_vjp(ctx, V, G_tau, Pt_tau, Pt_iw, Sinf_bar, Stau_bar, G_bar):
     """G_bar = J^H (Sinf_bar, Stau_bar) (torch's complex-gradient convention)."""
     pt, pw = (ctx.nk, ctx.ntau, ctx.naux, ctx.naux), (ctx.nk, ctx.nw_b, ctx.naux, ctx.naux)
     ctx._check(load().gw_sigma_vjp(
-        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
         _ptr(Pt_tau, "Pt_tau", pt), _ptr(Pt_iw, "Pt_iw", pw),
         _ptr(Sinf_bar, "Sinf_bar", ctx.k_shape()), _ptr(Stau_bar, "Stau_bar", ctx.g_shape()),
         _ptr(G_bar, "G_bar", ctx.g_shape())), "gw_sigma_vjp")
@@ -568,20 +568,20 @@ def gw_transform_adjoint(ctx, stat, inverse, X_in, X_out, batch=1):
 def gw_self_energy_vjp(ctx, V, G_tau, Pt_tau, Sig_bar, q0, nq, G_bar, Pt_bar):
     shp = (nq, ctx.ntau, ctx.naux, ctx.naux)
     ctx._check(load().gw_self_energy_vjp(
-        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
         _ptr(Pt_tau, "Pt_tau", shp), _ptr(Sig_bar, "Sig_bar", ctx.g_shape()), int(q0), int(nq),
         _ptr(G_bar, "G_bar", ctx.g_shape()), _ptr(Pt_bar, "Pt_bar", shp)), "gw_self_energy_vjp")
 
 
 def gw_polarization_vjp(ctx, V, G_tau, P0_bar, q0, nq, G_bar):
     ctx._check(load().gw_polarization_vjp(
-        ctx.h, _ptr(V, "V", ctx.v_shape()), _ptr(G_tau, "G_tau", ctx.g_shape()),
+        ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype), _ptr(G_tau, "G_tau", ctx.g_shape()),
         _ptr(P0_bar, "P0_bar", (nq, ctx.ntau, ctx.naux, ctx.naux)), int(q0), int(nq),
         _ptr(G_bar, "G_bar", ctx.g_shape())), "gw_polarization_vjp")
 
 
 def gw_hf_vjp(ctx, V, Sinf_bar, G_bar):
-    ctx._check(load().gw_hf_vjp(ctx.h, _ptr(V, "V", ctx.v_shape()),
+    ctx._check(load().gw_hf_vjp(ctx.h, _ptr(V, "V", ctx.v_shape(), ctx.v_dtype),
                                 _ptr(Sinf_bar, "Sinf_bar", ctx.k_shape()),
                                 _ptr(G_bar, "G_bar", ctx.g_shape())), "gw_hf_vjp")
 

@@ -114,19 +114,33 @@ def test_whole_chain_derivatives_match_oracle_autograd(case):
         assert rel(host(Gb), rb) < 1e-11
 
 
-def test_vjp_refuses_mixed_precision_and_workspace_checks(case):
+def test_mixed_vjp_through_abi_and_workspace_checks(case):
+    """gw_sigma_vjp in the complex64 contexts (per-q P~), called directly,
+    against the oracle's autograd; the binding refuses a complex128 V there;
+    then the workspace checks of the whole-chain calls."""
     from paper_2206_07660_amd import gw
     wl = case["wl"]
-    c = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, precision="fp32")
-    try:
-        z = dict(dtype=torch.complex128, device="cuda")
-        with pytest.raises(gw.GwError) as e:
-            gw.gw_sigma_vjp(c, dev(case["V"]), dev(case["G"]), None, None,
-                            torch.zeros(c.k_shape(), **z), torch.zeros(c.g_shape(), **z),
-                            torch.empty(c.g_shape(), **z))
-        assert e.value.status == gw.GW_ERR_ARG
-    finally:
-        c.close()
+    rng = np.random.default_rng(53)
+    Rb_inf = inp.circular_gaussian(rng, (wl.nk, wl.nao, wl.nao), 1.0)
+    Rb_tau = inp.circular_gaussian(rng, case["G"].shape, 1.0)
+    rb = ogt.vjp(case["V"], case["G"], Rb_inf, Rb_tau, case["g"], wl.mesh, NS)
+    z = dict(dtype=torch.complex128, device="cuda")
+    # complex64 rounding and fp32 products (~1e-6); bf16x3 forward P~ (~2^-17 per product)
+    for precision, bound in (("fp32", 1e-5), ("bf16x3", 1e-4)):
+        c = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, precision=precision, tau_chunk=5)
+        try:
+            with pytest.raises(TypeError):
+                gw.gw_sigma_vjp(c, dev(case["V"]), dev(case["G"]), None, None,
+                                torch.zeros(c.k_shape(), **z), torch.zeros(c.g_shape(), **z),
+                                torch.empty(c.g_shape(), **z))
+            Gb = torch.empty(c.g_shape(), **z)
+            gw.gw_sigma_vjp(c, dev(case["V"].astype(np.complex64)), dev(case["G"]), None, None,
+                            dev(Rb_inf), dev(Rb_tau), Gb)
+            err = np.abs(host(Gb) - rb).max() / np.abs(rb).max()
+            print(f"{precision} whole-chain VJP rel {err:.1e}")
+            assert 0 < err < bound
+        finally:
+            c.close()
     # a workspace too small for the per-q buffers of the whole-chain calls
     c = case["ctx"]
     L = gw.load()

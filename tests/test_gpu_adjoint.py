@@ -137,3 +137,49 @@ def test_autograd_at_general_complex_G(case):
     loss.backward()
     ref = ogt.vjp(d["V"], Gc, d["Sb_inf"], d["Sb_tau"], d["g"], d["wl"].mesh, NS)
     assert _rel(G.grad.cpu().numpy(), ref) < 1e-11
+
+
+# Relative bounds of the mixed-precision derivatives against the exact
+# (oracle) ones, relative to the largest entry: fp32 products and complex64
+# rounding of V, G and the intermediates (~1e-7 each, summed over long
+# contractions) give ~1e-6; the bf16x3 forward P~ carries ~2^-17 per product.
+MIXED_DERIV_REL = {"fp32": 1e-5, "bf16x3": 1e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("per_q", [False, True])
+def test_mixed_precision_vjp(precision, per_q):
+    """VJP and JVP in a complex64 context (complex64 V) against the oracle's
+    autograd, and the dot-product identity between them in that context."""
+    from paper_2206_07660_amd import gw
+    from paper_2206_07660_amd.adjoint import SigmaDerivatives
+    from paper_2206_07660_amd.scgw import GWPath
+    wl = inp.small_workload(mesh=(2, 2, 2), nao=6, naux=30, ntau=12, beta=8.0, seed=21)
+    g = og.Grids(wl.beta, wl.ntau)
+    H0, S, V = inp.make_H0(wl), inp.make_S(wl), inp.make_V(wl)
+    G = ogw.g0_tau(H0, S, 0.05, wl.beta, g.tau)
+    rng = np.random.default_rng(22)
+    dG = inp.random_hermitian_tau(rng, wl.ntau, wl.nk, wl.nao, 0.05)
+    Sb_inf = inp.circular_gaussian(rng, (wl.nk, wl.nao, wl.nao), 1.0)
+    Sb_tau = inp.circular_gaussian(rng, G.shape, 1.0)
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=5, precision=precision)
+    try:
+        path = GWPath(ctx, dev(V.astype(np.complex64)), dev(H0), dev(S), wl.n_target)
+        der = SigmaDerivatives(path, per_q=per_q)
+        Gd = dev(G)
+        s_inf, s_tau, Pt_tau, Pt_iw = der.forward(Gd)
+        Gb = der.vjp(Gd, Pt_tau, Pt_iw, dev(Sb_inf), dev(Sb_tau)).cpu().numpy()
+        di, ds = der.jvp(Gd, Pt_tau, Pt_iw, dev(dG))
+        di, ds = di.cpu().numpy(), ds.cpu().numpy()
+        ref = ogt.vjp(V, G, Sb_inf, Sb_tau, g, wl.mesh, NS)
+        ri, rs = ogt.jvp(V, G, dG, g, wl.mesh, NS)
+        lhs = np.vdot(Sb_inf.ravel(), di.ravel()) + np.vdot(Sb_tau.ravel(), ds.ravel())
+        rhs = np.vdot(Gb.ravel(), dG.ravel())
+        bound = MIXED_DERIV_REL[precision]
+        print(f"{precision} per_q={per_q}: vjp {_rel(Gb, ref):.1e} jvp {_rel(di, ri):.1e} {_rel(ds, rs):.1e} "
+              f"dot {abs(lhs - rhs) / abs(lhs):.1e}")
+        assert 0 < _rel(Gb, ref) < bound
+        assert _rel(di, ri) < bound and _rel(ds, rs) < bound
+        assert abs(lhs - rhs) < bound * abs(lhs)
+    finally:
+        ctx.close()

@@ -447,11 +447,10 @@ def test_descriptor_bounds_whole_path(small, monkeypatch):
                 path = GWPath(c, V, small["dH0"], small["dS"], wl.n_target, hermitian=herm)
                 s_inf, s_tau = path.sigma(small["dG"])
                 assert torch.isfinite(s_tau).all()
-                if precision == "fp64":
-                    der = SigmaDerivatives(path)
-                    si, st, Pt, Pw = der.forward(small["dG"])
-                    der.jvp(small["dG"], Pt, Pw, small["dG"])
-                    der.vjp(small["dG"], Pt, Pw, si, st)
+                der = SigmaDerivatives(path)
+                si, st, Pt, Pw = der.forward(small["dG"])
+                der.jvp(small["dG"], Pt, Pw, small["dG"])
+                der.vjp(small["dG"], Pt, Pw, si, st)
             st = path.start(small["mu0"])
             path.step(st)
             torch.cuda.synchronize()
