@@ -878,16 +878,17 @@ static gw_status pol_split_chunk(gw_ctx* c, const char* Aq, const char* Gd, cons
   gw_status s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * ldr});
   if (s != GW_OK) return s;
   g = gemm_desc();
-  g.A = Gbd + (size_t)(nt - 1 - t0) * nk * n2 * 8; g.B = Aq; g.C = Z;
+  // rows over tr = tcur-1-tl: G read with a positive stride (uniform-K loop)
+  g.A = Gbd + (size_t)(nt - t0 - tcur) * nk * n2 * 8; g.B = Aq; g.C = Z + (size_t)(tcur - 1) * ldr * 8;
   g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
-  g.am = two(nao, 1, -(long long)nk * n2); g.ak = aff(nao);
+  g.am = two(nao, 1, (long long)nk * n2); g.ak = aff(nao);
   g.bk = aff(nao); g.bn = two(nao, 1, n2); g.conjB = 1;
-  g.cm = two(nao, nao, ldr); g.cn = two(nao, 1, K);
+  g.cm = two(nao, nao, -ldr); g.cn = two(nao, 1, K);
   g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(n2);
   g.ta = g.tb = g.tc = 1; g.f32 = 1;
   g.tag = KC_POL_PRODUCER;
-  if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv},
-               Ext{0, (long long)tc * ldr})) != GW_OK)
+  if ((s = run(c, g, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)nk * sv},
+               Ext{-(long long)(tcur - 1) * ldr, (long long)(tc - tcur + 1) * ldr})) != GW_OK)
     return s;
   SplitDesc d = split_desc();
   d.A = X; d.B = Z; d.C = (double2*)P0 + ((long long)iq * nt + t0) * naux * naux;
@@ -968,16 +969,21 @@ static gw_status pol_impl(gw_ctx* c, const Work& w, const void* V, const gw_z* G
       gw_status s = run(c, g, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)tc * S});
       if (s != GW_OK) return s;
       // Zt[tl][k][Q'][d][b] = sum_c G[nt-1-t0-tl][k][c][d] conj(V[q][k][Q'][c][b])
+      // Rows run over tr = tcur-1-tl, so that G is read with a positive
+      // stride (the uniform-K loop needs non-negative operand strides) and
+      // the rows are written backwards.
       g = gemm_desc();
-      g.A = Gbd + (size_t)(nt - 1 - t0) * nk * n2 * ez; g.B = Aq; g.C = Z;
+      g.A = Gbd + (size_t)(nt - t0 - tcur) * nk * n2 * ez; g.B = Aq;
+      g.C = Z + (size_t)(tcur - 1) * S * ez;
       g.M = tcur * nao; g.N = naux * nao; g.K = nao; g.batch = nk;
-      g.am = two(nao, 1, -(long long)nk * n2); g.ak = aff(nao);
+      g.am = two(nao, 1, (long long)nk * n2); g.ak = aff(nao);
       g.bk = aff(nao); g.bn = two(nao, 1, n2); g.conjB = 1;
-      g.cm = two(nao, nao, S); g.cn = two(nao, 1, n2);
+      g.cm = two(nao, nao, -S); g.cn = two(nao, 1, n2);
       g.ba = aff(n2); g.bb = aff(sv); g.bc = aff(sv);
       g.ta = g.tb = g.tc = t; g.f32 = t;
       g.tag = KC_POL_PRODUCER;
-      if ((s = run(c, g, Ext{-(long long)(tcur - 1) * nk * n2, (long long)nk * n2}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tc * S})) != GW_OK) return s;
+      if ((s = run(c, g, Ext{0, (long long)tcur * nk * n2}, Ext{0, (long long)nk * sv},
+                   Ext{-(long long)(tcur - 1) * S, (long long)(tc - tcur + 1) * S})) != GW_OK) return s;
       // P0[q-q0][t0+tl][Q][Q'] = -(ns/nk) sum_{k,e} X[tl][k][Q][e] Zt[tl][k][Q'][e]
       g = gemm_desc();
       g.A = X; g.B = Z; g.C = (double2*)P0 + ((long long)(q - q0) * nt + t0) * naux * naux;

@@ -12,7 +12,8 @@ The workload is a plain device-to-device copy of a known size (calibration:
 the counters read in KiB per dispatch; the factor that makes them equal to
 the copy's 2 x N bytes is applied to every kernel) followed by one
 polarization call (one q, Hermitian mode) and one self-energy call at the
-si-4x4x4 shape, the launch configuration bench.py times.
+si-4x4x4 shape, the launch configuration bench.py times, in fp64 and then in
+the split-bf16 mode.
 """
 from __future__ import annotations
 
@@ -26,7 +27,9 @@ COPY_BYTES = 4 << 30
 # kernel-name prefixes (tile shape and class tag of zgemm_k) of the launches bench.py times
 CLASSES = {"pol_contract": "zgemm_k<2, 2, 1, 2, 2, 1,", "se_contract": "zgemm_k<2, 2, 1, 2, 4, 3,",
            "pol_producer": "zgemm_k<2, 2, 1, 2, 4, 2,", "se_producer": "zgemm_k<2, 2, 1, 2, 4, 4,",
-           "se_final": "zgemm_k<1, 1, 4, 2, 2, 5,"}
+           "se_final": "zgemm_k<1, 1, 4, 2, 2, 5,",
+           # split-bf16 contractions of the GW_PREC_BF16X3 path
+           "pol_contract_bf16x3": "bsgemm_k<2, 2, 2, 2, 1,", "se_contract_bf16x3": "bsgemm_k<2, 4, 4, 2, 3,"}
 
 
 def run():
@@ -49,6 +52,15 @@ def run():
     gw.gw_polarization(ctx, V, G, 0, 1, P)
     S = torch.zeros((wl.ntau, wl.nk, wl.nao, wl.nao), dtype=torch.complex128, device="cuda")
     gw.gw_self_energy(ctx, V, G, P, 0, 1, S)
+    torch.cuda.synchronize()
+    ctx.close()
+    # the same two calls in the split-bf16 mode (complex64 V)
+    V32 = V.to(torch.complex64)
+    del V
+    ctx = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, max_nq=1, precision="bf16x3")
+    gw.gw_set_hermitian(ctx, True)
+    gw.gw_polarization(ctx, V32, G, 0, 1, P)
+    gw.gw_self_energy(ctx, V32, G, P, 0, 1, S)
     torch.cuda.synchronize()
     ctx.close()
     print("traffic workload done", flush=True)
