@@ -177,7 +177,8 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl, precision="fp32"):
     n_s, ms_s, fl_s = prof["se_contract"]
     how = ("fp32 MFMA with fp64 chunk sums" if precision == "fp32" else
            "split-bf16 (bf16x3) MFMA for the polarization and P~ V contractions, fp32 MFMA for the "
-           "producers and the final self-energy contraction, fp64 chunk sums")
+           "producers and the final self-energy contraction (fp64 chunk sums there; the split "
+           "polarization sums its 512-term fp32 chunks in fp32)")
     res = {"sigma_eval_s_fp64": t64, "sigma_eval_s_mixed": t32, "speedup": t64 / t32,
            "evals_per_s_mixed": 1.0 / t32,
            "gflops_contractions_mixed": flops / t32 / 1e9,

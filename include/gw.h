@@ -84,7 +84,8 @@ enum { GW_FERMION = 0, GW_BOSON = 1 };
  *   run on bf16 MFMA with split operands: each real operand x is held as
  *   hi + lo, hi = bf16(x), lo = bf16(x - hi), and each real product as
  *   a_hi b_hi + a_hi b_lo + a_lo b_hi (relative error near 2^-16 per
- *   product), with fp32 accumulation and fp64 sums of 512-term chunks.     */
+ *   product), with fp32 accumulation; the polarization's long K is summed
+ *   as 512-term fp32 chunks added in fp32 (rounding near 1e-7 relative).   */
 enum { GW_PREC_FP64 = 0, GW_PREC_FP32 = 1, GW_PREC_BF16X3 = 2 };
 typedef struct { float re, im; } gw_c;
 

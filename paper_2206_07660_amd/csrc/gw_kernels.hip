@@ -777,8 +777,7 @@ hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
 // LDS row of a tile: 32 k as four planes [hi(re)][hi(im)][lo(re)][lo(im)] of
 // 8 x 4 bf16 (64 bytes each), rows kRowB bytes apart (16 bytes of padding
 // spread the rows of one fragment read over the banks); two stages, so the
-// splits of step s + 1 overlap the MFMAs of step s, while the global loads
-// run three steps ahead (two register slots).
+// global loads and splits of step s + 1 overlap the MFMAs of step s.
 // Loader: each thread owns chunks of 8 consecutive k of one row; with aks = 1
 // four threads read a row's 32 k (k-contiguous operands), otherwise
 // consecutive threads take consecutive rows (operands contiguous along the
@@ -787,7 +786,7 @@ hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
 // (column l % 16, same k, of B); the result holds column l % 16 and rows
 // 4 (l / 16) .. +3.  Waves: WM x WN tile the output, each BM x BN blocks.
 // SUMS: fp32 accumulation inside chunks of d.kchunk k, each chunk added into
-// fp64; without them (K <= kchunk) one fp32 chunk.
+// a SUMT (fp64 or fp32) sum; without them (K <= kchunk) one fp32 chunk.
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 static constexpr int kRowB = 272;
 
@@ -850,7 +849,7 @@ __device__ __forceinline__ void put_chunk(const Chunk<T>& c, unsigned char* row,
 }
 
 template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
-          int PF>
+          class SUMT>
 __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
   constexpr int NT = 64 * WM * WN, TM = WM * BM * 16, TN = WN * BN * 16;
   constexpr int CA = TM * 4 / NT, CB = TN * 4 / NT;   // loader chunks per thread
@@ -886,29 +885,24 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
     kb[u] = bcontig ? c & 3 : c / TN;
     pb[u] = B + map3(d.bn, (unsigned)min(tn0 + rb[u], d.N - 1));
   }
-  // PF (1 or 2) register slots of loaded chunks: the loads of step s + 1 + PF
-  // are issued during step s (with PF = 2 they are in flight during the
-  // MFMAs of two steps)
-  Chunk<TA> ca[PF][CA];
-  Chunk<TB> cb[PF][CB];
-  auto fetch = [&](int s, auto slot) {
-    constexpr int sl = decltype(slot)::value;
+  Chunk<TA> ca[CA];
+  Chunk<TB> cb[CB];
+  auto fetch = [&](int s) {
 #pragma unroll
-    for (int u = 0; u < CA; ++u) load_chunk<AK1>(ca[sl][u], pa[u], d.aks, 32 * s + 8 * ka[u], d.K);
+    for (int u = 0; u < CA; ++u) load_chunk<AK1>(ca[u], pa[u], d.aks, 32 * s + 8 * ka[u], d.K);
 #pragma unroll
-    for (int u = 0; u < CB; ++u) load_chunk<BK1>(cb[sl][u], pb[u], d.bks, 32 * s + 8 * kb[u], d.K);
+    for (int u = 0; u < CB; ++u) load_chunk<BK1>(cb[u], pb[u], d.bks, 32 * s + 8 * kb[u], d.K);
   };
-  auto stash = [&](auto slot, int stage) {
-    constexpr int sl = decltype(slot)::value;
+  auto stash = [&](int stage) {
     unsigned char* base = lds + stage * STAGE;
 #pragma unroll
-    for (int u = 0; u < CA; ++u) put_chunk(ca[sl][u], base + ra[u] * kRowB, ka[u]);
+    for (int u = 0; u < CA; ++u) put_chunk(ca[u], base + ra[u] * kRowB, ka[u]);
 #pragma unroll
-    for (int u = 0; u < CB; ++u) put_chunk(cb[sl][u], base + (TM + rb[u]) * kRowB, kb[u]);
+    for (int u = 0; u < CB; ++u) put_chunk(cb[u], base + (TM + rb[u]) * kRowB, kb[u]);
   };
 
   f4 accR[BM][BN], accN[BM][BN], accI[BM][BN];
-  double sumR[SUMS ? BM : 1][SUMS ? BN : 1][4], sumI[SUMS ? BM : 1][SUMS ? BN : 1][4];
+  SUMT sumR[SUMS ? BM : 1][SUMS ? BN : 1][4], sumI[SUMS ? BM : 1][SUMS ? BN : 1][4];
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -919,7 +913,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
 #pragma unroll
       for (int j = 0; j < BN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sumR[i][j][r] = sumI[i][j][r] = 0.0;
+        for (int r = 0; r < 4; ++r) sumR[i][j][r] = sumI[i][j][r] = SUMT(0);
   }
   auto promote = [&]() {
     if constexpr (SUMS) {
@@ -929,8 +923,8 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
         for (int j = 0; j < BN; ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            sumR[i][j][r] += (double)accR[i][j][r] - (double)accN[i][j][r];
-            sumI[i][j][r] += (double)accI[i][j][r];
+            sumR[i][j][r] += (SUMT)accR[i][j][r] - (SUMT)accN[i][j][r];
+            sumI[i][j][r] += (SUMT)accI[i][j][r];
           }
           accR[i][j] = accN[i][j] = accI[i][j] = f4{0, 0, 0, 0};
         }
@@ -992,45 +986,25 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
     terms(alr, ali, bhr, bhi);
   };
 
-  // step t's chunks live in register slot t % PF and LDS stage t % 2
+  // step t's chunks live in LDS stage t % 2; the loads of step s + 1 are
+  // issued before the MFMAs of step s
   const int nsteps = (d.K + 31) / 32;
   const int cper = d.kchunk / 32;
-  using S0 = std::integral_constant<int, 0>;
-  using S1 = std::integral_constant<int, PF - 1>;
-  if constexpr (PF == 1) {
-    fetch(0, S0{});
-    stash(S0{}, 0);
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    if (s + 1 < nsteps) fetch(s + 1);
+    compute(s & 1);
+    if (s + 1 < nsteps) stash((s + 1) & 1);
+    if ((s + 1) % cper == 0) promote();
     __syncthreads();
-    for (int s = 0; s < nsteps; ++s) {
-      if (s + 1 < nsteps) fetch(s + 1, S0{});
-      compute(s & 1);
-      if (s + 1 < nsteps) stash(S0{}, (s + 1) & 1);
-      if ((s + 1) % cper == 0) promote();
-      __syncthreads();
-    }
-  } else {
-    fetch(0, S0{});
-    stash(S0{}, 0);
-    if (nsteps > 1) fetch(1, S1{});
-    if (nsteps > 2) fetch(2, S0{});
-    __syncthreads();
-    auto step = [&](int s, auto next) {           // next: slot of step s + 1
-      compute(s & 1);
-      if (s + 1 < nsteps) stash(next, (s + 1) & 1);
-      if (s + 3 < nsteps) fetch(s + 3, next);
-      if ((s + 1) % cper == 0) promote();
-      __syncthreads();
-    };
-    for (int s = 0; s < nsteps; s += 2) {
-      step(s, S1{});
-      if (s + 1 < nsteps) step(s + 1, S0{});
-    }
   }
   promote();
 
   // epilogue: fp32 MFMA result layout, rows 4 (lane / 16) + r, column lane % 16
   auto res = [&](int i, int j, int r, bool im) -> double {
-    if constexpr (SUMS) return im ? sumI[i][j][r] : sumR[i][j][r];
+    if constexpr (SUMS) return im ? (double)sumI[i][j][r] : (double)sumR[i][j][r];
     else return im ? (double)accI[i][j][r] : (double)accR[i][j][r] - (double)accN[i][j][r];
   };
   TC* C = (TC*)d.C + map3(d.bc, tp.bt);
@@ -1068,7 +1042,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
 }
 
 template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
-          int PF>
+          class SUMT = double>
 static hipError_t bs_cfg(const SplitDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tm_ = (d0.M + TM - 1) / TM;
@@ -1082,14 +1056,18 @@ static hipError_t bs_cfg(const SplitDesc& d0, hipStream_t st) {
   d.q_tiles = udiv_make((unsigned)tiles);
   d.q_batch = udiv_make((unsigned)d.batch);
   if ((d0.aks == 1) != AK1 || (d0.bks == 1) != BK1) return hipErrorInvalidValue;
-  bsgemm_k<WM, WN, BM, BN, TAG, TA, TB, TC, SUMS, AK1, BK1, PF><<<dim3((unsigned)(tiles * d.batch)), 64 * WM * WN, 0, st>>>(d);
+  bsgemm_k<WM, WN, BM, BN, TAG, TA, TB, TC, SUMS, AK1, BK1, SUMT><<<dim3((unsigned)(tiles * d.batch)), 64 * WM * WN, 0, st>>>(d);
   return hipGetLastError();
 }
 
 // Tile configurations (d.cfg < 0: the default of the role).  Polarization
-// (complex64 operands, long K with fp64 chunk sums, square tiles for the
-// Hermitian mode): 64x64 on 4 waves, loads three steps ahead.  Self-energy
-// P~ V (complex64 P~ and V, K = naux <= kchunk; loads one step ahead):
+// (complex64 operands, long K, square tiles for the Hermitian mode): 64x64 on
+// 4 waves, the 512-term fp32 chunks summed in fp32:
+// 229 VGPRs, so two workgroups share a CU (7.2 ms per q at si-4x4x4, against
+// 10.9 ms with fp64 chunk sums and loads three steps ahead, 309 VGPRs, one
+// workgroup per CU; the outer fp32 sum's rounding, ~1e-7 relative, is far
+// below the bf16x3 product error).  Self-energy
+// P~ V (complex64 P~ and V, K = naux <= kchunk):
 // 0 128x128 on 8 waves (4 x 2 blocks each), 1 64x64 on 4 waves, 2 128x64 on
 // 4 waves (4 x 2).
 hipError_t bsgemm_launch(const SplitDesc& d, hipStream_t st) {
@@ -1098,13 +1076,13 @@ hipError_t bsgemm_launch(const SplitDesc& d, hipStream_t st) {
   // the polarization's operands have K contiguous; the self-energy's V has
   // K = Q' with stride n2
   if (d.tag == KC_POL_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 0)
-    return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, 2>(d, st);
+    return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, float>(d, st);
   if (d.tag == KC_SE_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 1) {
-    if (d.K > d.kchunk) return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false, 1>(d, st);
+    if (d.K > d.kchunk) return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false>(d, st);
     switch (d.cfg) {
-      case 1: return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, 1>(d, st);
-      case 2: return bs_cfg<2, 2, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, 1>(d, st);
-      default: return bs_cfg<2, 4, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, 1>(d, st);
+      case 1: return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false>(d, st);
+      case 2: return bs_cfg<2, 2, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false>(d, st);
+      default: return bs_cfg<2, 4, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false>(d, st);
     }
   }
   return hipErrorInvalidValue;
