@@ -665,6 +665,16 @@ static bool uniform_k(const GemmDesc& d, unsigned kstep, long long ea, long long
   return va + ka + ea <= lim && vb + kb + eb <= lim;
 }
 
+// The fp64 polarization contraction (uniform-K loop) reserves LDS it does
+// not use, so that at most two workgroups share a CU: the tiles of one tau
+// then drift less apart in K and meet more often in L2 (measured at
+// si-4x4x4: 24.0 ms per launch against 25.5 ms with four workgroups per CU
+// and 32.0 ms with one).
+template <int TAG, bool F32>
+static constexpr size_t residency_lds() {
+  return (TAG == KC_POL_CONTRACT && !F32) ? size_t(60000) : size_t(0);
+}
+
 template <int WM, int WN, int WK, int BM, int BN, int TAG, class TA, class TB, class TC, bool F32>
 static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
@@ -684,7 +694,7 @@ static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   if (F32 && d.kchunk > 0 && d.kchunk % kstep) return hipErrorInvalidValue;
   constexpr int nt = 64 * WM * WN * WK;
   if (uniform_k(d, kstep, sizeof(TA), sizeof(TB)))
-    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
+    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32><<<grid, nt, residency_lds<TAG, F32>(), st>>>(d);
   else if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
     zgemm_k<WM, WN, WK, BM, BN, TAG, 1, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
   else
