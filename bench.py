@@ -176,9 +176,10 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl, precision="fp32"):
     n_l, ms_l, fl_l = prof["pol_contract"]
     n_s, ms_s, fl_s = prof["se_contract"]
     how = ("fp32 MFMA with fp64 chunk sums" if precision == "fp32" else
-           "split-bf16 (bf16x3) MFMA for the polarization and P~ V contractions, fp32 MFMA for the "
-           "producers and the final self-energy contraction (fp64 chunk sums there; the split "
-           "polarization sums its 512-term fp32 chunks in fp32)")
+           ("split-bf16 (%s) MFMA for the polarization and P~ V contractions, fp32 MFMA for the "
+            "producers and the final self-energy contraction (fp64 chunk sums there; the split "
+            "polarization sums its 512-term fp32 chunks in %s)"
+            % (precision, "fp32" if precision == "bf16x3" else "fp64")))
     res = {"sigma_eval_s_fp64": t64, "sigma_eval_s_mixed": t32, "speedup": t64 / t32,
            "evals_per_s_mixed": 1.0 / t32,
            "gflops_contractions_mixed": flops / t32 / 1e9,
@@ -190,6 +191,17 @@ def mixed_comparison(ctx64, path64, st, V, H0, S, wl, precision="fp32"):
                         "; transforms, screened-interaction solve, HF, Dyson, mu in fp64"}
     if precision == "fp32":
         res["fp32_mfma_frac_path"] = flops / t32 / 157.3e12
+    else:
+        # bf16x3 / bf16x6 run three / six bf16 products per real product: the
+        # fraction of the dense bf16 MFMA peak (2.5 PFLOP/s) the two split
+        # contractions reach, and their rate against the fp32 MFMA peak
+        # (157.3 TFLOP/s)
+        nprod = 3.0 if precision == "bf16x3" else 6.0
+        for name, (n_c, ms_c, fl_c) in (("pol_contract", prof["pol_contract"]), ("se_contract", prof["se_contract"])):
+            if ms_c:
+                rate = fl_c / (ms_c * 1e-3)
+                res[name + "_bf16_mfma_frac"] = nprod * rate / 2.5e15
+                res[name + "_vs_fp32_peak"] = rate / 157.3e12
     ctx32.close()
     del V32, p32
     torch.cuda.empty_cache()
@@ -516,7 +528,7 @@ def main():
                     help="grand-canonical solves: mu found for N_target at G0, then held")
     ap.add_argument("--solve", choices=["damped", "diis", "nk"],
                     help="instead of the step benchmark: one self-consistent solve to --tol")
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3", "bf16x6"], default="fp64",
                     help="precision of the --solve path")
     ap.add_argument("--ir", action="store_true", help="--solve on IR grids (lambda = beta * --ir-wmax)")
     ap.add_argument("--per-q", action="store_true", help="Newton-Krylov with P~ rebuilt per q")
@@ -668,6 +680,7 @@ def main():
     if not args.no_mixed:
         out["mixed_fp32"] = mixed_comparison(ctx, path, st, V, H0, S, wl, "fp32")
         out["mixed_bf16x3"] = mixed_comparison(ctx, path, st, V, H0, S, wl, "bf16x3")
+        out["mixed_bf16x6"] = mixed_comparison(ctx, path, st, V, H0, S, wl, "bf16x6")
     if not args.no_ir:
         out["ir_grids"] = ir_comparison(path, V, H0, S, wl, wl.beta * args.ir_wmax, args.ir_eps, ms_step)
     if not args.no_cpu_baseline:

@@ -85,8 +85,11 @@ enum { GW_FERMION = 0, GW_BOSON = 1 };
  *   hi + lo, hi = bf16(x), lo = bf16(x - hi), and each real product as
  *   a_hi b_hi + a_hi b_lo + a_lo b_hi (relative error near 2^-16 per
  *   product), with fp32 accumulation; the polarization's long K is summed
- *   as 512-term fp32 chunks added in fp32 (rounding near 1e-7 relative).   */
-enum { GW_PREC_FP64 = 0, GW_PREC_FP32 = 1, GW_PREC_BF16X3 = 2 };
+ *   as 512-term fp32 chunks added in fp32 (rounding near 1e-7 relative).
+ * GW_PREC_BF16X6: as GW_PREC_BF16X3 with three levels, x = hi + mid + lo,
+ *   and the six level products up to second order (relative error near
+ *   2^-24, that of fp32), fp32 chunks added in fp64.                      */
+enum { GW_PREC_FP64 = 0, GW_PREC_FP32 = 1, GW_PREC_BF16X3 = 2, GW_PREC_BF16X6 = 3 };
 typedef struct { float re, im; } gw_c;
 
 typedef struct {

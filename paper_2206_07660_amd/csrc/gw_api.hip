@@ -102,7 +102,7 @@ gw_status check_dims(const gw_dims* d, std::string& why) {
   }
   if (d->ns != 1 && d->ns != 2) { why = "ns must be 1 or 2"; return GW_ERR_ARG; }
   if (!(d->beta > 0.0) || !std::isfinite(d->beta)) { why = "beta must be positive"; return GW_ERR_ARG; }
-  if (d->precision != GW_PREC_FP64 && d->precision != GW_PREC_FP32 && d->precision != GW_PREC_BF16X3) {
+  if (d->precision < GW_PREC_FP64 || d->precision > GW_PREC_BF16X6) {
     why = "unsupported precision";
     return GW_ERR_ARG;
   }
@@ -635,10 +635,13 @@ gw_status gw_get_grids(const gw_ctx* cc, double* tau, long long* nF, long long* 
 // Bytes of the polarization / self-energy chains for a tau chunk: two
 // intermediates of tc x Nk x naux x nao^2 (plus complex64 copies of two G
 // arrays in mixed precision).
-// complex64 V and chain intermediates (GW_PREC_FP32, GW_PREC_BF16X3)
+// complex64 V and chain intermediates (GW_PREC_FP32, GW_PREC_BF16X3, GW_PREC_BF16X6)
 static bool lowp(const gw_ctx* c) { return c->d.precision != GW_PREC_FP64; }
-// split-bf16 operands of the two large contractions (GW_PREC_BF16X3)
-static bool splitbf(const gw_ctx* c) { return c->d.precision == GW_PREC_BF16X3; }
+// split-bf16 operands of the two large contractions (GW_PREC_BF16X3, GW_PREC_BF16X6)
+static bool splitbf(const gw_ctx* c) {
+  return c->d.precision == GW_PREC_BF16X3 || c->d.precision == GW_PREC_BF16X6;
+}
+static int nsplit(const gw_ctx* c) { return c->d.precision == GW_PREC_BF16X6 ? 3 : 2; }
 // Chain workspace: two tau-chunk regions (X and Zt, or Vt and L); in the
 // low-precision modes two complex64 copies of G after them.
 static size_t region_bytes(const gw_ctx* c, int tc) {
@@ -852,7 +855,7 @@ gw_status gw_polarization_noalloc(gw_ctx* c, const void* V, const gw_z* G, int q
   return s;
 }
 
-// One tau chunk of Eq. tilde_P0_tau in the split-bf16 mode (GW_PREC_BF16X3).
+// One tau chunk of Eq. tilde_P0_tau in the split-bf16 modes (GW_PREC_BF16X3 / X6).
 // The complex64 producers write X and Zt with K = (k, d, b) contiguous per
 // row, so that the contraction's loader reads whole K-runs:
 //   X2[tl][Q][k n2 + d nao + b]  = sum_a V[q][k][Q][d][a] G[t0+tl][k+q][a][b]
@@ -899,7 +902,7 @@ static gw_status pol_split_chunk(gw_ctx* c, const char* Aq, const char* Gd, cons
   d.cm = aff(naux); d.cn = aff(1);
   d.alpha_r = -(double)c->d.ns / nk;
   if (accumulate) { d.beta_zero = 0; d.beta_r = 1.0; }
-  d.tri = herm ? 1 : 0; d.kchunk = kMixedChunk;
+  d.tri = herm ? 1 : 0; d.kchunk = kMixedChunk; d.nsplit = nsplit(c);
   d.tag = KC_POL_CONTRACT;
   if ((s = run_split(c, d, Ext{0, (long long)tcur * ldr}, Ext{0, (long long)tcur * ldr},
                      Ext{0, (long long)tcur * naux * naux})) != GW_OK)
@@ -1176,7 +1179,7 @@ gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt
         d.bn = two((unsigned)n2, 1, sv); d.bks = n2; d.bb = aff(0);
         d.cm = aff(n2); d.cn = two((unsigned)n2, 1, sv); d.bc = aff(S);
         d.batch_fastest = 1;                    // every tau reads the same V slab
-        d.kchunk = kMixedChunk;
+        d.kchunk = kMixedChunk; d.nsplit = nsplit(c);
         d.tag = KC_SE_CONTRACT;
         gw_status s = run_split(c, d, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv},
                                 Ext{0, (long long)tcur * S});

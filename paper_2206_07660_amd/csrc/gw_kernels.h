@@ -90,7 +90,7 @@ static inline GemmDesc gemm_desc() {
   return d;
 }
 
-// Split-bf16 complex GEMM (bsgemm_k, bf16x3 with operands split in LDS):
+// Split-bf16 complex GEMM (bsgemm_k, bf16x3 or bf16x6 with operands split in LDS):
 // C[b](m, n) = alpha * sum_k A[b](m, k) B[b](n, k) + beta * C[b](m, n) with
 // A(m, k) = A[ba(b) + am(m) + k aks] and B(n, k) = B[bb(b) + bn(n) + k bks].
 // Offsets count complex elements of the operand's storage type.
@@ -112,6 +112,7 @@ struct SplitDesc {
   int kchunk;         // fp32 accumulation length before the fp64 sum (multiple of 32)
   int tag;            // KC_POL_CONTRACT or KC_SE_CONTRACT
   int cfg;            // tile configuration (see bsgemm_launch)
+  int nsplit;         // bf16 levels per real operand: 2 (bf16x3) or 3 (bf16x6)
   Udiv q_tiles_m, q_tiles, q_batch;
 };
 
@@ -124,6 +125,7 @@ static inline SplitDesc split_desc() {
   d.batch = 1;
   d.kchunk = 512;
   d.cfg = -1;
+  d.nsplit = 2;
   return d;
 }
 

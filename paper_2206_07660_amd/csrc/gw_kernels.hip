@@ -778,16 +778,19 @@ hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
 // contractions:  C[b](m, n) = alpha * sum_k A[b](m, k) B[b](n, k) + beta C[b](m, n)
 // with A(m, k) = A[ba(b) + am(m) + k aks] and B(n, k) = B[bb(b) + bn(n) + k bks],
 // complex128 or complex64 in memory.  Each K-step of 32 brings the A and B
-// tiles into LDS, splitting every real part x on the way into hi = bf16(x)
-// and lo = bf16(x - hi) (16 significant bits together); each real product is
-// then a_hi b_hi + a_hi b_lo + a_lo b_hi on v_mfma_f32_16x16x32_bf16 (the
-// dropped a_lo b_lo and the split residuals are near 2^-17 |a b|).  The
-// Im(a) Im(b) part of Re(a b) accumulates on its own and is subtracted at the
-// end of each chunk, so the loop has no sign flips.
-// LDS row of a tile: 32 k as four planes [hi(re)][hi(im)][lo(re)][lo(im)] of
-// 8 x 4 bf16 (64 bytes each), rows kRowB bytes apart (16 bytes of padding
-// spread the rows of one fragment read over the banks); two stages, so the
-// global loads and splits of step s + 1 overlap the MFMAs of step s.
+// tiles into LDS, splitting every real part x on the way into NS bf16 levels
+// (round to nearest even): NS = 2, x = hi + lo with hi = bf16(x),
+// lo = bf16(x - hi) (16 significant bits); NS = 3, x = hi + mid + lo (24).
+// A real product is the sum of the level products a_u b_v with u + v < NS on
+// v_mfma_f32_16x16x32_bf16: a_hi b_hi + a_hi b_lo + a_lo b_hi (bf16x3; the
+// dropped terms and residuals are near 2^-17 |a b|), or the six products up
+// to u + v = 2 (bf16x6, near 2^-24, the fp32 rounding).  The Im(a) Im(b)
+// part of Re(a b) accumulates on its own and is subtracted at the end of each
+// chunk, so the loop has no sign flips.
+// LDS row of a tile: 32 k as 2 NS planes [level 0 re][level 0 im][level 1
+// re]... of 8 x 4 bf16 (64 bytes each), rows row_bytes(NS) apart (16 bytes of
+// padding spread the rows of one fragment read over the banks); two stages,
+// so the global loads and splits of step s + 1 overlap the MFMAs of step s.
 // Loader: each thread owns chunks of 8 consecutive k of one row; with aks = 1
 // four threads read a row's 32 k (k-contiguous operands), otherwise
 // consecutive threads take consecutive rows (operands contiguous along the
@@ -798,7 +801,7 @@ hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
 // SUMS: fp32 accumulation inside chunks of d.kchunk k, each chunk added into
 // a SUMT (fp64 or fp32) sum; without them (K <= kchunk) one fp32 chunk.
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-static constexpr int kRowB = 272;
+template <int NS> static constexpr int row_bytes() { return 128 * NS + 16; }
 
 template <class T> struct Chunk;
 template <> struct Chunk<float2> { float2 v[8]; };
@@ -830,8 +833,9 @@ __device__ __forceinline__ void load_chunk(Chunk<T>& c, const T* p, long long ks
   }
 }
 
-// split 8 complex values and write the four planes of one LDS chunk
-template <class T>
+// split 8 complex values into NS levels and write the 2 NS planes of one LDS
+// chunk (16 bytes each, 64 bytes apart)
+template <int NS, class T>
 __device__ __forceinline__ void put_chunk(const Chunk<T>& c, unsigned char* row, int kgc) {
   float re[8], im[8];
 #pragma unroll
@@ -839,28 +843,32 @@ __device__ __forceinline__ void put_chunk(const Chunk<T>& c, unsigned char* row,
     re[e] = (float)c.v[e].x;
     im[e] = (float)c.v[e].y;
   }
-  uint4 hr, hi, lr, li;
-  unsigned* phr = (unsigned*)&hr;
-  unsigned* phi = (unsigned*)&hi;
-  unsigned* plr = (unsigned*)&lr;
-  unsigned* pli = (unsigned*)&li;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    phr[i] = pack_bf16(re[2 * i], re[2 * i + 1]);
-    phi[i] = pack_bf16(im[2 * i], im[2 * i + 1]);
-    plr[i] = pack_bf16(re[2 * i] - bf16_low(phr[i]), re[2 * i + 1] - bf16_high(phr[i]));
-    pli[i] = pack_bf16(im[2 * i] - bf16_low(phi[i]), im[2 * i + 1] - bf16_high(phi[i]));
-  }
   uint4* q = (uint4*)(row + 16 * kgc);
-  q[0] = hr;
-  q[4] = hi;
-  q[8] = lr;
-  q[12] = li;
+#pragma unroll
+  for (int l = 0; l < NS; ++l) {
+    uint4 pr, pi;
+    unsigned* ur = (unsigned*)&pr;
+    unsigned* ui = (unsigned*)&pi;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ur[i] = pack_bf16(re[2 * i], re[2 * i + 1]);
+      ui[i] = pack_bf16(im[2 * i], im[2 * i + 1]);
+      if (l + 1 < NS) {                 // residuals for the next level
+        re[2 * i] -= bf16_low(ur[i]);
+        re[2 * i + 1] -= bf16_high(ur[i]);
+        im[2 * i] -= bf16_low(ui[i]);
+        im[2 * i + 1] -= bf16_high(ui[i]);
+      }
+    }
+    q[8 * l] = pr;
+    q[8 * l + 4] = pi;
+  }
 }
 
 template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
-          class SUMT>
+          class SUMT, int NS>
 __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
+  constexpr int kRowB = row_bytes<NS>();
   constexpr int NT = 64 * WM * WN, TM = WM * BM * 16, TN = WN * BN * 16;
   constexpr int CA = TM * 4 / NT, CB = TN * 4 / NT;   // loader chunks per thread
   static_assert(CA >= 1 && CB >= 1 && CA * NT == TM * 4 && CB * NT == TN * 4, "loader split");
@@ -906,9 +914,9 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
   auto stash = [&](int stage) {
     unsigned char* base = lds + stage * STAGE;
 #pragma unroll
-    for (int u = 0; u < CA; ++u) put_chunk(ca[u], base + ra[u] * kRowB, ka[u]);
+    for (int u = 0; u < CA; ++u) put_chunk<NS>(ca[u], base + ra[u] * kRowB, ka[u]);
 #pragma unroll
-    for (int u = 0; u < CB; ++u) put_chunk(cb[u], base + (TM + rb[u]) * kRowB, kb[u]);
+    for (int u = 0; u < CB; ++u) put_chunk<NS>(cb[u], base + (TM + rb[u]) * kRowB, kb[u]);
   };
 
   f4 accR[BM][BN], accN[BM][BN], accI[BM][BN];
@@ -966,34 +974,26 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
   auto compute = [&](int stage) {
     const unsigned char* base = lds + stage * STAGE;
     const int ra0 = wm * BM * 16, rb0 = TM + wn * BN * 16;
-    uint4 ahr[BM], ahi[BM], bhr[BN], bhi[BN];
+    // all B levels, then A level by level with the B levels v < NS - u
+    uint4 br[NS][BN], bi[NS][BN];
 #pragma unroll
-    for (int i = 0; i < BM; ++i) {
-      ahr[i] = rd(base, ra0 + 16 * i, 0);
-      ahi[i] = rd(base, ra0 + 16 * i, 1);
-    }
-#pragma unroll
-    for (int j = 0; j < BN; ++j) {
-      bhr[j] = rd(base, rb0 + 16 * j, 0);
-      bhi[j] = rd(base, rb0 + 16 * j, 1);
-    }
-    terms(ahr, ahi, bhr, bhi);
-    {
-      uint4 blr[BN], bli[BN];
+    for (int l = 0; l < NS; ++l)
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        blr[j] = rd(base, rb0 + 16 * j, 2);
-        bli[j] = rd(base, rb0 + 16 * j, 3);
+        br[l][j] = rd(base, rb0 + 16 * j, 2 * l);
+        bi[l][j] = rd(base, rb0 + 16 * j, 2 * l + 1);
       }
-      terms(ahr, ahi, blr, bli);
-    }
-    uint4 alr[BM], ali[BM];
 #pragma unroll
-    for (int i = 0; i < BM; ++i) {
-      alr[i] = rd(base, ra0 + 16 * i, 2);
-      ali[i] = rd(base, ra0 + 16 * i, 3);
+    for (int u = 0; u < NS; ++u) {
+      uint4 ar[BM], ai[BM];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        ar[i] = rd(base, ra0 + 16 * i, 2 * u);
+        ai[i] = rd(base, ra0 + 16 * i, 2 * u + 1);
+      }
+#pragma unroll
+      for (int v = 0; v + u < NS; ++v) terms(ar, ai, br[v], bi[v]);
     }
-    terms(alr, ali, bhr, bhi);
   };
 
   // step t's chunks live in LDS stage t % 2; the loads of step s + 1 are
@@ -1052,7 +1052,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
 }
 
 template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
-          class SUMT = double>
+          class SUMT, int NS>
 static hipError_t bs_cfg(const SplitDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tm_ = (d0.M + TM - 1) / TM;
@@ -1066,7 +1066,7 @@ static hipError_t bs_cfg(const SplitDesc& d0, hipStream_t st) {
   d.q_tiles = udiv_make((unsigned)tiles);
   d.q_batch = udiv_make((unsigned)d.batch);
   if ((d0.aks == 1) != AK1 || (d0.bks == 1) != BK1) return hipErrorInvalidValue;
-  bsgemm_k<WM, WN, BM, BN, TAG, TA, TB, TC, SUMS, AK1, BK1, SUMT><<<dim3((unsigned)(tiles * d.batch)), 64 * WM * WN, 0, st>>>(d);
+  bsgemm_k<WM, WN, BM, BN, TAG, TA, TB, TC, SUMS, AK1, BK1, SUMT, NS><<<dim3((unsigned)(tiles * d.batch)), 64 * WM * WN, 0, st>>>(d);
   return hipGetLastError();
 }
 
@@ -1085,14 +1085,28 @@ hipError_t bsgemm_launch(const SplitDesc& d, hipStream_t st) {
   if (d.K <= 0 || d.kchunk <= 0 || d.kchunk % 32) return hipErrorInvalidValue;
   // the polarization's operands have K contiguous; the self-energy's V has
   // K = Q' with stride n2
+  if (d.nsplit == 3) {
+    // bf16x6: fp64 chunk sums (the products are as accurate as fp32 ones);
+    // 64 x 64 tiles, as 128 x 128 ones would need 205 KB of LDS
+    if (d.tag == KC_POL_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 0)
+      return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, double, 3>(d, st);
+    if (d.tag == KC_SE_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 1) {
+      if (d.K > d.kchunk)
+        return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false, double, 3>(d, st);
+      return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, double, 3>(d, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (d.nsplit != 2) return hipErrorInvalidValue;
   if (d.tag == KC_POL_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 0)
-    return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, float>(d, st);
+    return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, float, 2>(d, st);
   if (d.tag == KC_SE_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 1) {
-    if (d.K > d.kchunk) return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false>(d, st);
+    if (d.K > d.kchunk)
+      return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false, double, 2>(d, st);
     switch (d.cfg) {
-      case 1: return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false>(d, st);
-      case 2: return bs_cfg<2, 2, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false>(d, st);
-      default: return bs_cfg<2, 4, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false>(d, st);
+      case 1: return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, double, 2>(d, st);
+      case 2: return bs_cfg<2, 2, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, double, 2>(d, st);
+      default: return bs_cfg<2, 4, 4, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, double, 2>(d, st);
     }
   }
   return hipErrorInvalidValue;

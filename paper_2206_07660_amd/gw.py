@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libgw.so")
 (GW_OK, GW_ERR_ARG, GW_ERR_DEVICE, GW_ERR_SINGULAR, GW_ERR_NOCONV, GW_ERR_WORKSPACE, GW_ERR_STATE,
  GW_ERR_NONFINITE) = range(8)
 GW_FERMION, GW_BOSON = 0, 1
-GW_PREC_FP64, GW_PREC_FP32, GW_PREC_BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": GW_PREC_FP64, "fp32": GW_PREC_FP32, "bf16x3": GW_PREC_BF16X3}
+GW_PREC_FP64, GW_PREC_FP32, GW_PREC_BF16X3, GW_PREC_BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp64": GW_PREC_FP64, "fp32": GW_PREC_FP32, "bf16x3": GW_PREC_BF16X3, "bf16x6": GW_PREC_BF16X6}
 (GW_OP_POLARIZATION, GW_OP_SELF_ENERGY, GW_OP_SCREENED_W, GW_OP_HF, GW_OP_DYSON_JVP, GW_OP_SIGMA,
  GW_OP_THERMO) = range(7)
 KCLASS = dict(other=0, pol_contract=1, pol_producer=2, se_contract=3, se_producer=4,

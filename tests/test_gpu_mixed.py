@@ -1,6 +1,6 @@
 """Mixed-precision paths (complex fp32 MFMA contractions, or split-bf16
-bf16x3 for the two large ones; fp64 transforms, solves and mu) against the
-fp64 oracle.  The stated bound is 1e-6 Ha on the max-abs error of Sigma =
+bf16x3 / bf16x6 for the two large ones; fp64 transforms, solves and mu)
+against the fp64 oracle.  The stated bound is 1e-6 Ha on the max-abs error of Sigma =
 Sigma_inf + Sigma~; the error of G after one Dyson step is bounded by what
 such a Sigma error can do to first order (1e-6 max ||G(i w)||_2^2), that of a
 band-edge proxy (eigenvalues of H0 + Sigma_inf + Herm Sigma~(i w_0), highest
@@ -28,7 +28,7 @@ def band_edges(H0, sinf, siw0, n_occ):
     return e[:, n_occ - 1].max(), e[:, n_occ].min()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("name", ["tiny-2x2x2", "ragged"])
 def test_mixed_sigma_error(name, precision):
     from paper_2206_07660_amd import gw
