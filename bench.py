@@ -252,19 +252,36 @@ def ir_comparison(path, V, H0, S, wl, lam, eps, ms_step_cheb):
         p_ir.step(st_i)
     torch.cuda.synchronize()
     ms_ir = 1e3 * (time.perf_counter() - t0) / steps
+    # the same IR grids with the split-bf16 contractions (complex64 V)
+    G_ir = st_i.G_tau.clone()
+    ctx_ir.close()
+    del p_ir
+    torch.cuda.empty_cache()
+    V32 = V.to(torch.complex64)
+    ctx_b = gw.Context(wl.mesh, wl.nao, wl.naux, None, wl.beta, ns=wl.ns, ir=(lam, eps), precision="bf16x3")
+    p_b = GWPath(ctx_b, V32, H0, S, wl.n_target)
+    p_b.sigma(G_ir)                                    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p_b.sigma(G_ir)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    ctx_b.close()
+    del p_b, V32
+    torch.cuda.empty_cache()
     res = {"lambda": lam, "eps": eps, "ntau": ctx_ir.ntau, "nw_f": ctx_ir.nw_f, "nw_b": ctx_ir.nw_b,
            "ntau_chebyshev": path.ctx.ntau,
            "sigma_eval_s_chebyshev": t_c, "sigma_eval_s_ir": t_i, "evals_per_s_ir": 1.0 / t_i,
            "speedup_eval": t_c / t_i, "ms_per_step_ir": ms_ir, "speedup_step": ms_step_cheb / ms_ir,
            "max_abs_dSigma_inf_Ha": float(np.abs(si_c - si_i).max()),
            "max_abs_dSigma_iw_common_Ha": d_iw, "common_frequencies": len(common),
+           "sigma_eval_s_ir_bf16x3": t_b, "speedup_eval_ir_bf16x3_over_chebyshev_fp64": t_c / t_b,
            "note": "G0 of H0 at the same mu on each grid; Sigma~(i w) compared where the sparse sets "
-                   "share Matsubara indices; the IR step then runs its own mu search"}
-    ctx_ir.close()
-    del p_ir
-    torch.cuda.empty_cache()
+                   "share Matsubara indices; the IR step then runs its own mu search; the bf16x3 "
+                   "evaluation is on the IR grids from the G of the IR steps"}
     log(f"[bench] IR grids (ntau {res['ntau']}): {t_i:.2f} s vs Chebyshev ({path.ctx.ntau}) {t_c:.2f} s per "
-        f"evaluation, step {ms_ir:.0f} ms; max|dSigma| {res['max_abs_dSigma_inf_Ha']:.1e} / {d_iw}")
+        f"evaluation, step {ms_ir:.0f} ms; max|dSigma| {res['max_abs_dSigma_inf_Ha']:.1e} / {d_iw}; "
+        f"IR + bf16x3 {t_b:.2f} s")
     return res
 
 
