@@ -35,7 +35,8 @@ def test_status_strings():
 @pytest.mark.parametrize("field,value", [("nao", 0), ("nao", 61), ("ntau", 7), ("ns", 3),
                                          ("nw_f", 5), ("nw_b", 10), ("nw_f", 97), ("nw_b", 98),
                                          ("beta", -1.0),
-                                         ("naux", 0), ("precision", 9)])
+                                         ("naux", 0), ("precision", 9), ("precision", 4),
+                                         ("precision", -1)])
 def test_create_rejects_bad_dims_without_gpu(field, value):
     L = gw.load()
     d = gw.Dims((ctypes.c_int * 3)(2, 2, 2), 6, 24, 24, 24, 25, 2, 0, 50.0)

@@ -65,14 +65,16 @@ def test_edge_shape_chain(name):
         assert np.abs(Gt.cpu().numpy() - ogw.to_tau(g.TFp, Giw_r)).max() < TOL
     finally:
         c.close()
-    # mixed precision on the same shape
-    c32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=5,
-                     precision="fp32")
-    try:
-        path = GWPath(c32, dev(V.astype(np.complex64)), dev(H0), dev(S), wl.n_target)
-        sinf, stau = path.sigma(dev(G))
-        e = max(np.abs(sinf.cpu().numpy() - r_inf).max(), np.abs(stau.cpu().numpy() - r_tau).max())
-        print(f"{name} mixed: max |dSigma| {e:.2e}")
-        assert e < 1e-6
-    finally:
-        c32.close()
+    # the mixed-precision modes on the same shape (the split modes' loader
+    # masks K past nao^2 Nk and naux, their tiles clamp rows past naux)
+    for precision in ("fp32", "bf16x3", "bf16x6"):
+        c32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=NS, tau_chunk=5,
+                         precision=precision)
+        try:
+            path = GWPath(c32, dev(V.astype(np.complex64)), dev(H0), dev(S), wl.n_target)
+            sinf, stau = path.sigma(dev(G))
+            e = max(np.abs(sinf.cpu().numpy() - r_inf).max(), np.abs(stau.cpu().numpy() - r_tau).max())
+            print(f"{name} {precision}: max |dSigma| {e:.2e}")
+            assert e < 1e-6
+        finally:
+            c32.close()
