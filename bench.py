@@ -436,7 +436,7 @@ def begin(path, start):
 def compare_precisions(path64, V, H0, S, wl, tol, presolve_tol=1e-4):
     """Whole self-consistent solves to max |Sigma[G(x)] - x| < tol: the plain
     damped fp64 loop, DIIS and Newton-Krylov in fp64 and DIIS in the mixed
-    path (complex64 V, fp32 MFMA contractions); seconds, evaluations, and how
+    path (complex64 V; fp32 MFMA and split-bf16 bf16x3 contractions); seconds, evaluations, and how
     far the fixed points lie apart (equal-accuracy check).  With a
     grand-canonical path64 (fixed_mu) every solver starts from one canonical
     DIIS pre-solve to presolve_tol and holds its mu, so that all of them
@@ -453,6 +453,8 @@ def compare_precisions(path64, V, H0, S, wl, tol, presolve_tol=1e-4):
            "workload": wl.name, "tol_max_abs_residual_Ha": tol, "fixed_mu": fixed}
     ctx32 = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision="fp32")
     p32 = GWPath(ctx32, V.to(torch.complex64), H0, S, wl.n_target, fixed_mu=fixed)
+    ctxbf = gw.Context(wl.mesh, wl.nao, wl.naux, wl.ntau, wl.beta, ns=wl.ns, precision="bf16x3")
+    pbf = GWPath(ctxbf, p32.V, H0, S, wl.n_target, fixed_mu=fixed)
     start = None
     if fixed:
         torch.cuda.synchronize()
@@ -477,7 +479,7 @@ def compare_precisions(path64, V, H0, S, wl, tol, presolve_tol=1e-4):
                           "seconds": time.perf_counter() - t0, "final_dsigma": st.dsig, "mu": st.mu,
                           "n_e": st.n_e}
     sols["fp64_damped"] = (st.sig_inf.clone(), st.sig_tau.clone())
-    for name, p in (("fp64_diis", path64), ("mixed_diis", p32)):
+    for name, p in (("fp64_diis", path64), ("mixed_diis", p32), ("bf16x3_diis", pbf)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s0 = begin(p, start)
@@ -511,9 +513,12 @@ def compare_precisions(path64, V, H0, S, wl, tol, presolve_tol=1e-4):
     out["max_abs_sigma_fp64_diis_vs_damped_Ha"] = d(sols["fp64_diis"], ref)
     out["max_abs_sigma_fp64_nk_vs_damped_Ha"] = d(sols["fp64_nk"], ref)
     out["max_abs_sigma_mixed_vs_fp64_Ha"] = d(sols["mixed_diis"], sols["fp64_diis"])
-    for k in ("fp64_diis", "mixed_diis", "fp64_nk"):
+    out["max_abs_sigma_bf16x3_vs_fp64_Ha"] = d(sols["bf16x3_diis"], sols["fp64_diis"])
+    for k in ("fp64_diis", "mixed_diis", "bf16x3_diis", "fp64_nk"):
         out[f"speedup_{k}_over_damped"] = out["fp64_damped"]["seconds"] / out[k]["seconds"]
     out["speedup_mixed_over_fp64_diis"] = out["fp64_diis"]["seconds"] / out["mixed_diis"]["seconds"]
+    out["speedup_bf16x3_over_fp64_diis"] = out["fp64_diis"]["seconds"] / out["bf16x3_diis"]["seconds"]
+    ctxbf.close()
     ctx32.close()
     return out
 
