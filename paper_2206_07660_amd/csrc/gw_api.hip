@@ -215,15 +215,17 @@ gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
   gw_status s = prof_begin(c, g.tag, &e0);
   if (s != GW_OK) return s;
   GemmDesc gg = g;
-  // tile shapes measured best on MI355X at naux = 250: 64x64 for the
-  // polarization contraction, 64x128 for the self-energy one
-  gg.cfg = c->tile_cfg >= 0 ? c->tile_cfg : (g.tag == KC_SE_CONTRACT ? 1 : 0);
+  // tile shapes measured best on MI355X at naux = 250, both on the
+  // three-product (Gauss) form: 64x64 for the polarization contraction,
+  // 64x96 for the self-energy one
+  gg.cfg = c->tile_cfg >= 0 ? c->tile_cfg : (g.tag == KC_SE_CONTRACT ? 7 : 5);
   hipError_t e = zgemm_launch(gg, c->st);
   if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("zgemm: ") + hipGetErrorString(e));
-  // algorithmic flops: 8 real flops per complex multiply-add
-  // useful flops: with g.tri only the entries on and above the diagonal
+  // MFMA flops executed: 8 real flops per complex multiply-add, 6 on the
+  // three-product form; with g.tri only the entries on and above the diagonal
   const double outs = g.tri ? 0.5 * g.M * (g.M + 1.0) : (double)g.M * g.N;
-  return prof_end(c, g.tag, e0, 8.0 * outs * g.K * g.batch);
+  const double per = zgemm_three_product(gg) ? 6.0 : 8.0;
+  return prof_end(c, g.tag, e0, per * outs * g.K * g.batch);
 }
 
 // Split-bf16 contraction: eA, eB, eC the valid element ranges of the

@@ -145,6 +145,9 @@ struct DysonArgs {
 };
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st);
+// true when zgemm_launch runs d on the three-product (Gauss) form: 6 real
+// MFMA flops per complex multiply-add instead of 8
+bool zgemm_three_product(const GemmDesc& d);
 hipError_t bsgemm_launch(const SplitDesc& d, hipStream_t st);
 hipError_t dyson_launch(const DysonArgs& a, int nw, hipStream_t st);
 hipError_t sum_launch(const double* x, long long n, double scale, double* out, hipStream_t st);

@@ -242,9 +242,15 @@ __device__ __forceinline__ float flip(float x, unsigned m) {
 // KM: K-loop form.  0 general index maps (any number of carries per step);
 // 1 at most one carry per digit and step; 2 "uniform" (see launch_cfg): the
 // K offset is a wave-uniform scalar and each lane keeps a constant offset.
+// G3 (fp64, uniform-K loop): the complex product on three real MFMAs
+// (Gauss): P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi), then
+// re = P1 - P2 and im = P3 - P1 - P2.  A quarter fewer MFMAs for a third
+// accumulator set; the rounding error stays a few ulps of sum |a| |b|.
 template <int WM, int WN, int WK, int BM, int BN, int TAG, int KM, class TA, class TB, class TC,
-          bool F32>
+          bool F32, bool G3 = false>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
+  static_assert(!(G3 && F32), "the three-product form is fp64 only");
+  constexpr bool M3 = G3 && KM == 2;
   typedef Mfma<F32> MM;
   typedef typename MM::S S;
   typedef typename MM::S2 S2;
@@ -282,7 +288,7 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     boff[j] = bv[j] ? map3(d.bn, n) : 0;
   }
 
-  Acc accR[BM][BN], accI[BM][BN];
+  Acc accR[BM][BN], accI[BM][BN], accN[M3 ? BM : 1][M3 ? BN : 1];
   double sumR[F32 ? BM : 1][F32 ? BN : 1][4], sumI[F32 ? BM : 1][F32 ? BN : 1][4];
 #pragma unroll
   for (int i = 0; i < BM; ++i)
@@ -290,6 +296,7 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     for (int j = 0; j < BN; ++j) {
       accR[i][j] = Acc{0, 0, 0, 0};
       accI[i][j] = Acc{0, 0, 0, 0};
+      if constexpr (M3) accN[i][j] = Acc{0, 0, 0, 0};
     }
   if constexpr (F32) {
 #pragma unroll
@@ -457,6 +464,22 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
         br[j] = b[j].x;
         bi[j] = flip(b[j].y, mb);
       }
+      if constexpr (M3) {
+        S as[BM], bs[BN];
+#pragma unroll
+        for (int i = 0; i < BM; ++i) as[i] = ar[i] + ai[i];
+#pragma unroll
+        for (int j = 0; j < BN; ++j) bs[j] = br[j] + bi[j];
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BN; ++j) {
+            accR[i][j] = MM::run(ar[i], br[j], accR[i][j]);
+            accN[i][j] = MM::run(ai[i], bi[j], accN[i][j]);
+            accI[i][j] = MM::run(as[i], bs[j], accI[i][j]);
+          }
+        return;
+      }
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -538,6 +561,8 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
   // lane-local result, fp64
   auto res = [&](int i, int j, int r, bool im) -> double {
     if constexpr (F32) return im ? sumI[i][j][r] : sumR[i][j][r];
+    else if constexpr (M3)
+      return im ? accI[i][j][r] - accR[i][j][r] - accN[i][j][r] : accR[i][j][r] - accN[i][j][r];
     else return im ? accI[i][j][r] : accR[i][j][r];
   };
 
@@ -675,7 +700,8 @@ static constexpr size_t residency_lds() {
   return (TAG == KC_POL_CONTRACT && !F32) ? size_t(60000) : size_t(0);
 }
 
-template <int WM, int WN, int WK, int BM, int BN, int TAG, class TA, class TB, class TC, bool F32>
+template <int WM, int WN, int WK, int BM, int BN, int TAG, class TA, class TB, class TC, bool F32,
+          bool G3 = false>
 static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tm_ = (d0.M + TM - 1) / TM;
@@ -694,7 +720,7 @@ static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   if (F32 && d.kchunk > 0 && d.kchunk % kstep) return hipErrorInvalidValue;
   constexpr int nt = 64 * WM * WN * WK;
   if (uniform_k(d, kstep, sizeof(TA), sizeof(TB)))
-    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32><<<grid, nt, residency_lds<TAG, F32>(), st>>>(d);
+    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32, G3><<<grid, nt, residency_lds<TAG, F32>(), st>>>(d);
   else if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
     zgemm_k<WM, WN, WK, BM, BN, TAG, 1, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
   else
@@ -703,10 +729,15 @@ static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
 }
 
 // Tile shape: 32 x 32 with four-way split K for small outputs; 64 x 128 for
-// the producers; otherwise 64 x 64, or for the two large contractions the
-// configuration in d.cfg
+// the producers; otherwise 64 x 64, or for the two large fp64 contractions
+// the configuration in d.cfg
 // (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x64 on eight waves, 4: 64x64 with
-// two-way split K).
+// two-way split K; 5..9 the three-product form on 64x64, 64x128, 64x96,
+// 128x64 on eight waves, 128x64).  Measured at si-4x4x4 (ms per q, fp64):
+// polarization 23.8 (0) vs 22.3 (5); self-energy 31.7 (1) vs 26.3 (7),
+// 26.7 (5), 28.6 (8), 34.5 (6), 35.2 (9) -- 6 and 9 need more than 256
+// VGPRs and run one wave per SIMD.  The producers (K = nao) gain nothing
+// from it (11.7 vs 12.0 ms), their stores bound them.
 template <int TAG, class TA, class TB, class TC, bool F32>
 static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 32 && d.N <= 32) return launch_cfg<1, 1, 4, 2, 2, TAG, TA, TB, TC, F32>(d, st);
@@ -716,6 +747,11 @@ static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
       case 2: return launch_cfg<2, 2, 1, 4, 2, TAG, TA, TB, TC, F32>(d, st);
       case 3: return launch_cfg<4, 2, 1, 2, 2, TAG, TA, TB, TC, F32>(d, st);
       case 4: return launch_cfg<2, 2, 2, 2, 2, TAG, TA, TB, TC, F32>(d, st);
+      case 5: return launch_cfg<2, 2, 1, 2, 2, TAG, TA, TB, TC, F32, true>(d, st);
+      case 6: return launch_cfg<2, 2, 1, 2, 4, TAG, TA, TB, TC, F32, true>(d, st);
+      case 7: return launch_cfg<2, 2, 1, 2, 3, TAG, TA, TB, TC, F32, true>(d, st);
+      case 8: return launch_cfg<4, 2, 1, 2, 2, TAG, TA, TB, TC, F32, true>(d, st);
+      case 9: return launch_cfg<2, 2, 1, 4, 2, TAG, TA, TB, TC, F32, true>(d, st);
       default: break;
     }
   }
@@ -756,6 +792,12 @@ static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
     if (code == (8 | 2 | 4)) return launch_typed<TAG, double2, float2, float2, true>(d, st);
   }
   return hipErrorInvalidValue;
+}
+
+bool zgemm_three_product(const GemmDesc& d) {
+  if (d.f32 || (d.tag != KC_POL_CONTRACT && d.tag != KC_SE_CONTRACT)) return false;
+  if (d.cfg < 5 || d.cfg > 9 || (d.M <= 32 && d.N <= 32)) return false;
+  return uniform_k(d, 4u, d.ta ? 8 : 16, d.tb ? 8 : 16);
 }
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {

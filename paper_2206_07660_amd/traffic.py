@@ -25,7 +25,7 @@ import sys
 
 COPY_BYTES = 4 << 30
 # kernel-name prefixes (tile shape and class tag of zgemm_k) of the launches bench.py times
-CLASSES = {"pol_contract": "zgemm_k<2, 2, 1, 2, 2, 1,", "se_contract": "zgemm_k<2, 2, 1, 2, 4, 3,",
+CLASSES = {"pol_contract": "zgemm_k<2, 2, 1, 2, 2, 1,", "se_contract": "zgemm_k<2, 2, 1, 2, 3, 3,",
            "pol_producer": "zgemm_k<2, 2, 1, 2, 4, 2,", "se_producer": "zgemm_k<2, 2, 1, 2, 4, 4,",
            "se_final": "zgemm_k<1, 1, 4, 2, 2, 5,",
            # split-bf16 contractions of the GW_PREC_BF16X3 path
