@@ -42,11 +42,12 @@
  * Environment (read by gw_create).  GW_DEBUG_BOUNDS=1 makes every call check
  *   on the host, before launching, that each GEMM descriptor it builds stays
  *   inside the extents of its operands (a failed check returns GW_ERR_ARG);
- *   GW_TILE_CFG=0..9 forces the tile shape of the two large fp64 contractions
- *   (measurement only): 0..4 the four-product complex MFMA form, 5..9 the
- *   three-product (Gauss) form, the default (5 for the polarization, 7 for
- *   the self-energy); the Hermitian polarization needs a square shape: 0, 4
- *   or 5.
+ *   GW_TILE_CFG=0..10 forces the tile shape of the two large fp64
+ *   contractions (measurement only): 0..4 the four-product complex MFMA form,
+ *   5..10 the three-product (Gauss) form, the default (5 for the
+ *   polarization, 10 for the self-energy); the Hermitian polarization needs
+ *   a square shape: 0, 4 or 5.  GW_PROD_TILES=1 runs the fp32 producers on
+ *   the tiled GEMM instead of the streaming kernel (measurement only).
  */
 #ifndef GW_H
 #define GW_H

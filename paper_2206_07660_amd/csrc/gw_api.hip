@@ -43,6 +43,7 @@ struct gw_ctx {
   std::vector<int> plus;   // host copy of the k+q table
   bool check_bounds = false;
   int tile_cfg = -1;       // tile configuration of the large contractions (-1: default)
+  int prod_tiles = 0;      // 1: fp32 producers on the tiled GEMM instead of the streaming kernel
   int split_cfg = -1;      // tile configuration of the split-bf16 contractions
   int split_group = 0;     // > 0: grouped workgroup order of the split contractions
   int herm = 0;            // gw_set_hermitian: GW_HERM_* bits
@@ -217,8 +218,9 @@ gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
   GemmDesc gg = g;
   // tile shapes measured best on MI355X at naux = 250, both on the
   // three-product (Gauss) form: 64x64 for the polarization contraction,
-  // 64x96 for the self-energy one
-  gg.cfg = c->tile_cfg >= 0 ? c->tile_cfg : (g.tag == KC_SE_CONTRACT ? 7 : 5);
+  // 64x96 with loads two K-steps ahead for the self-energy one
+  if (g.tag == KC_POL_PRODUCER || g.tag == KC_SE_PRODUCER) gg.cfg = c->prod_tiles;
+  else gg.cfg = c->tile_cfg >= 0 ? c->tile_cfg : (g.tag == KC_SE_CONTRACT ? 10 : 5);
   hipError_t e = zgemm_launch(gg, c->st);
   if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("zgemm: ") + hipGetErrorString(e));
   // MFMA flops executed: 8 real flops per complex multiply-add, 6 on the
@@ -356,6 +358,8 @@ gw_status gw_create(const gw_dims* d, void* hip_stream, gw_ctx** out) {
     c->check_bounds = e && e[0] == '1';
     const char* t = std::getenv("GW_TILE_CFG");
     c->tile_cfg = t ? std::atoi(t) : -1;
+    const char* pt = std::getenv("GW_PROD_TILES");
+    c->prod_tiles = pt && pt[0] == '1' ? 1 : 0;
     const char* u = std::getenv("GW_SPLIT_CFG");
     c->split_cfg = u ? std::atoi(u) : -1;
     const char* gg = std::getenv("GW_SPLIT_GROUP");

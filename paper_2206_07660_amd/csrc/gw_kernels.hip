@@ -246,9 +246,12 @@ __device__ __forceinline__ float flip(float x, unsigned m) {
 // (Gauss): P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi), then
 // re = P1 - P2 and im = P3 - P1 - P2.  A quarter fewer MFMAs for a third
 // accumulator set; the rounding error stays a few ulps of sum |a| |b|.
+// NB: register stages of the uniform-K loop (2: loads one K-step ahead of the
+// MFMAs, 3: two steps ahead).
 template <int WM, int WN, int WK, int BM, int BN, int TAG, int KM, class TA, class TB, class TC,
-          bool F32, bool G3 = false>
+          bool F32, bool G3 = false, int NB = 2>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
+  static_assert(NB == 2 || NB == 3, "two or three register stages");
   static_assert(!(G3 && F32), "the three-product form is fp64 only");
   constexpr bool M3 = G3 && KM == 2;
   typedef Mfma<F32> MM;
@@ -503,19 +506,47 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     // steps whose four k are all below K
     const unsigned nfull = kfirst + 4u <= K ? (K - kfirst - 4u) / kstep + 1u : 0u;
     unsigned s = 0;
-    if (nfull) ldf(a0, b0);
-    for (; s + 2 <= nfull; s += 2) {
-      ldf(a1, b1);
-      mmf(a0, b0);
-      pc(s);
-      if (s + 2 < nfull) ldf(a0, b0);
-      mmf(a1, b1);
-      pc(s + 1);
-    }
-    if (s < nfull) {
-      mmf(a0, b0);
-      pc(s);
-      ++s;
+    if constexpr (NB == 2) {
+      if (nfull) ldf(a0, b0);
+      for (; s + 2 <= nfull; s += 2) {
+        ldf(a1, b1);
+        mmf(a0, b0);
+        pc(s);
+        if (s + 2 < nfull) ldf(a0, b0);
+        mmf(a1, b1);
+        pc(s + 1);
+      }
+      if (s < nfull) {
+        mmf(a0, b0);
+        pc(s);
+        ++s;
+      }
+    } else {
+      // step t lives in buffer t % 3; loads are issued in step order
+      S2 a2[BM], b2[BN];
+      if (nfull > 0) ldf(a0, b0);
+      if (nfull > 1) ldf(a1, b1);
+      for (; s + 3 <= nfull; s += 3) {
+        ldf(a2, b2);
+        mmf(a0, b0);
+        pc(s);
+        if (s + 3 < nfull) ldf(a0, b0);
+        mmf(a1, b1);
+        pc(s + 1);
+        if (s + 4 < nfull) ldf(a1, b1);
+        mmf(a2, b2);
+        pc(s + 2);
+      }
+      if (s < nfull) {
+        mmf(a0, b0);
+        pc(s);
+        ++s;
+      }
+      if (s < nfull) {
+        mmf(a1, b1);
+        pc(s);
+        ++s;
+      }
     }
     if (s < nsteps) {
       // last, partial step: lanes with k >= K read zeros
@@ -659,6 +690,188 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     store(std::false_type{});
 }
 
+// ---------------------------------------------------------------------------
+// Producers with short K (K <= 32, e.g. X = V G with K = nao): the GemmDesc
+// product of zgemm_k (index maps, batch tables, conjugation, alpha, beta),
+// organised for an output-bound product.  Each wave keeps the A fragments of
+// its 32 rows for all K-steps in registers and walks a run of 16-column
+// blocks: the B fragments of the next block load while the MFMAs of the
+// current block run and its results are stored, so operand loads, MFMAs and
+// stores of consecutive blocks overlap.  Used for the fp32-MFMA producers;
+// with fp64 MFMA the tiled kernel stays ahead (see launch_typed).
+// KS (the K-steps of 4) is a compile-time count, so that no load or MFMA
+// sits under a branch: a branch there makes every use of a prefetched
+// fragment wait for all outstanding memory operations, stores included.
+// Rows past M and k past K contribute zeros; loads of clamped rows, columns
+// and k stay inside the operands.
+constexpr int kProdRows = 128;    // rows per workgroup: 4 waves x 32
+constexpr int kProdBlocks = 16;   // 16-column blocks per workgroup
+
+template <int TAG, int KS, class TA, class TB, class TC, bool F32>
+__global__ void __launch_bounds__(256) prod_k(GemmDesc d) {
+  typedef Mfma<F32> MM;
+  typedef typename MM::S S;
+  typedef typename MM::S2 S2;
+  typedef typename MM::Acc Acc;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, kl = lane >> 4;
+  // XCD-contiguous logical id (as tile_pos), decomposed as (run fastest,
+  // row tile, batch entry): consecutive workgroups share the A rows of a row
+  // tile, and a batch entry's B stays in its XCD's L2
+  const unsigned w = blockIdx.x, total = gridDim.x;
+  const unsigned xcd = w % 8u, slot = w / 8u, per = total / 8u, rem = total % 8u;
+  const unsigned logical = xcd < rem ? xcd * (per + 1u) + slot : rem * (per + 1u) + (xcd - rem) * per + slot;
+  const unsigned bt = udiv(logical, d.q_tiles);
+  const unsigned rest = logical - bt * d.q_tiles.d;
+  const unsigned tm = udiv(rest, d.q_tiles_m);
+  const unsigned run = rest - tm * d.q_tiles_m.d;
+
+  const TA* A = (const TA*)d.A + batch_off(d.ba, d.tab, d.q_tmod, d.tsA, bt);
+  const TB* B = (const TB*)d.B + batch_off(d.bb, d.tab, d.q_tmod, d.tsB, bt);
+  TC* C = (TC*)d.C + batch_off(d.bc, d.tab, d.q_tmod, d.tsC, bt);
+  const int K = d.K;
+  const unsigned ma = d.conjA ? 0x80000000u : 0u, mb = d.conjB ? 0x80000000u : 0u;
+  const int m0 = (int)tm * kProdRows + wave * 32;
+
+  S ar[2][KS], ai[2][KS];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = m0 + i * 16 + r16;
+    const bool mv = m < d.M;
+    const long long ao = map3(d.am, (unsigned)(mv ? m : d.M - 1));
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = 4 * s + kl;
+      const bool ok = mv && k < K;
+      const S2 v = MM::cvt(A[ao + map3(d.ak, (unsigned)(k < K ? k : K - 1))]);
+      ar[i][s] = ok ? v.x : S(0);
+      ai[i][s] = ok ? flip(v.y, ma) : S(0);
+    }
+  }
+  long long bko[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + kl;
+    bko[s] = map3(d.bk, (unsigned)(k < K ? k : K - 1));
+  }
+  long long ro[2][4];
+  bool rok[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + i * 16 + MM::row(kl, r);
+      rok[i][r] = m < d.M;
+      ro[i][r] = rok[i][r] ? map3(d.cm, (unsigned)m) : 0;
+    }
+
+  auto ldb = [&](S (&br)[KS], S (&bi)[KS], int jb) {
+    const int n = min(jb * 16 + r16, d.N - 1);
+    const long long bo = map3(d.bn, (unsigned)n);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const S2 v = MM::cvt(B[bo + bko[s]]);
+      br[s] = v.x;
+      bi[s] = flip(v.y, mb);
+    }
+  };
+  // PLAIN: alpha = 1 and beta = 0, without the scaling and the read of C
+  auto blk = [&](const S (&br)[KS], const S (&bi)[KS], int jb, auto plain) {
+    Acc cr[2], ci[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) cr[i] = ci[i] = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        cr[i] = MM::run(ar[i][s], br[s], cr[i]);
+        ci[i] = MM::run(ar[i][s], bi[s], ci[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        cr[i] = MM::run_neg(ai[i][s], bi[s], cr[i]);
+        ci[i] = MM::run(ai[i][s], br[s], ci[i]);
+      }
+    }
+    const int n = jb * 16 + r16;
+    if (n >= d.N) return;
+    const long long con = map3(d.cn, (unsigned)n);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (!rok[i][r]) continue;
+        const long long o = ro[i][r] + con;
+        const double xr = (double)cr[i][r], xi = (double)ci[i][r];
+        double2 v;
+        if constexpr (decltype(plain)::value) {
+          v.x = xr;
+          v.y = xi;
+        } else {
+          v.x = d.alpha_r * xr - d.alpha_i * xi;
+          v.y = d.alpha_r * xi + d.alpha_i * xr;
+          if (!d.beta_zero) {
+            const double2 c = to_d2(C[o]);
+            v.x += d.beta_r * c.x - d.beta_i * c.y;
+            v.y += d.beta_r * c.y + d.beta_i * c.x;
+          }
+        }
+        C[o] = from_d2<TC>(v);
+      }
+  };
+
+  // j0 < j1: run < ceil(nblk / kProdBlocks).  The prefetches are not under
+  // a branch (the block index is clamped; the last one goes unused), or the
+  // compiler waits for them right after issuing them.
+  const int nblk = (d.N + 15) / 16;
+  const int j0 = (int)run * kProdBlocks, j1 = min(j0 + kProdBlocks, nblk);
+  auto walk = [&](auto plain) {
+    S br0[KS], bi0[KS], br1[KS], bi1[KS];
+    int jb = j0;
+    ldb(br0, bi0, jb);
+    for (; jb + 2 <= j1; jb += 2) {
+      ldb(br1, bi1, jb + 1);
+      // keep the prefetch ahead of this block's MFMAs (the scheduler would
+      // sink it into them and shorten its cover)
+      __builtin_amdgcn_sched_barrier(0);
+      blk(br0, bi0, jb, plain);
+      ldb(br0, bi0, min(jb + 2, j1 - 1));
+      __builtin_amdgcn_sched_barrier(0);
+      blk(br1, bi1, jb + 1, plain);
+    }
+    if (jb < j1) blk(br0, bi0, jb, plain);
+  };
+  if (d.beta_zero && d.alpha_r == 1.0 && d.alpha_i == 0.0)
+    walk(std::true_type{});
+  else
+    walk(std::false_type{});
+}
+
+template <int TAG, class TA, class TB, class TC, bool F32>
+static hipError_t launch_prod(const GemmDesc& d0, hipStream_t st) {
+  GemmDesc d = d0;
+  if (d.K > 32 || d.tri || d.tmod <= 0) return hipErrorInvalidValue;
+  const long long tiles_m = (d.M + kProdRows - 1) / kProdRows;
+  const long long nrun = ((d.N + 15) / 16 + kProdBlocks - 1) / kProdBlocks;
+  const long long total = tiles_m * nrun * d.batch;
+  if (tiles_m * nrun > 0x7fffffffLL || total > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  d.q_tiles_m = udiv_make((unsigned)nrun);
+  d.q_tiles = udiv_make((unsigned)(tiles_m * nrun));
+  d.q_batch = udiv_make((unsigned)d.batch);
+  d.q_tmod = udiv_make((unsigned)d.tmod);
+  const dim3 grid((unsigned)total, 1, 1);
+  if (d.K <= 8)
+    prod_k<TAG, 2, TA, TB, TC, F32><<<grid, 256, 0, st>>>(d);
+  else if (d.K <= 16)
+    prod_k<TAG, 4, TA, TB, TC, F32><<<grid, 256, 0, st>>>(d);
+  else if (d.K <= 28)
+    prod_k<TAG, 7, TA, TB, TC, F32><<<grid, 256, 0, st>>>(d);
+  else
+    prod_k<TAG, 8, TA, TB, TC, F32><<<grid, 256, 0, st>>>(d);
+  return hipGetLastError();
+}
+
 static bool one_carry(const Map3& m, unsigned st) {
   return m.din >= st && (unsigned long long)m.din * m.dmid >= st;
 }
@@ -701,7 +914,7 @@ static constexpr size_t residency_lds() {
 }
 
 template <int WM, int WN, int WK, int BM, int BN, int TAG, class TA, class TB, class TC, bool F32,
-          bool G3 = false>
+          bool G3 = false, int NB = 2>
 static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tm_ = (d0.M + TM - 1) / TM;
@@ -720,7 +933,7 @@ static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   if (F32 && d.kchunk > 0 && d.kchunk % kstep) return hipErrorInvalidValue;
   constexpr int nt = 64 * WM * WN * WK;
   if (uniform_k(d, kstep, sizeof(TA), sizeof(TB)))
-    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32, G3><<<grid, nt, residency_lds<TAG, F32>(), st>>>(d);
+    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32, G3, NB><<<grid, nt, residency_lds<TAG, F32>(), st>>>(d);
   else if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
     zgemm_k<WM, WN, WK, BM, BN, TAG, 1, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
   else
@@ -733,10 +946,11 @@ static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
 // the configuration in d.cfg
 // (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x64 on eight waves, 4: 64x64 with
 // two-way split K; 5..9 the three-product form on 64x64, 64x128, 64x96,
-// 128x64 on eight waves, 128x64).  Measured at si-4x4x4 (ms per q, fp64):
-// polarization 23.8 (0) vs 22.3 (5); self-energy 31.7 (1) vs 26.3 (7),
-// 26.7 (5), 28.6 (8), 34.5 (6), 35.2 (9) -- 6 and 9 need more than 256
-// VGPRs and run one wave per SIMD.  The producers (K = nao) gain nothing
+// 128x64 on eight waves, 128x64; 10 = 7 with loads two K-steps ahead).
+// Measured at si-4x4x4 (ms per q, fp64): polarization 23.8 (0) vs 22.3 (5),
+// 23.2 with loads two steps ahead; self-energy 31.7 (1) vs 26.0 (7), 25.4
+// (10), 26.7 (5), 28.6 (8), 34.5 (6), 35.2 (9) -- 6 and 9 need more than
+// 256 VGPRs and run one wave per SIMD.  The producers (K = nao) gain nothing
 // from it (11.7 vs 12.0 ms), their stores bound them.
 template <int TAG, class TA, class TB, class TC, bool F32>
 static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
@@ -752,6 +966,7 @@ static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
       case 7: return launch_cfg<2, 2, 1, 2, 3, TAG, TA, TB, TC, F32, true>(d, st);
       case 8: return launch_cfg<4, 2, 1, 2, 2, TAG, TA, TB, TC, F32, true>(d, st);
       case 9: return launch_cfg<2, 2, 1, 4, 2, TAG, TA, TB, TC, F32, true>(d, st);
+      case 10: return launch_cfg<2, 2, 1, 2, 3, TAG, TA, TB, TC, F32, true, 3>(d, st);
       default: break;
     }
   }
@@ -760,11 +975,17 @@ static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
   // 20.5 ms (polarization) and 22.6 vs 26.0 ms (self-energy) per q
   if constexpr ((TAG == KC_POL_CONTRACT || TAG == KC_SE_CONTRACT) && F32)
     return launch_cfg<2, 2, 2, 2, 2, TAG, TA, TB, TC, F32>(d, st);
-  // the producers (K = nao): 64 x 128 tiles give each wave twice the MFMA work
-  // per load latency (measured 12.6 vs 14.0 ms per polarization call at
-  // si-4x4x4)
-  if constexpr (TAG == KC_POL_PRODUCER || TAG == KC_SE_PRODUCER)
+  // the producers (K = nao): fp32 MFMA (complex64 intermediates) on the
+  // streaming kernel (measured 7.7 vs 8.2 ms per polarization call and 3.8
+  // vs 4.0 ms per self-energy producer at si-4x4x4); fp64 on 64 x 128 tiles,
+  // which give each wave twice the MFMA work per load latency of 64 x 64
+  // ones (12.6 vs 14.0 ms) and beat the streaming kernel (11.7 vs 12.9 ms)
+  if constexpr (TAG == KC_POL_PRODUCER || TAG == KC_SE_PRODUCER) {
+    if constexpr (F32) {
+      if (d.K <= 32 && !d.tri && d.cfg != 1) return launch_prod<TAG, TA, TB, TC, F32>(d, st);
+    }
     return launch_cfg<2, 2, 1, 2, 4, TAG, TA, TB, TC, F32>(d, st);
+  }
   return launch_cfg<2, 2, 1, 2, 2, TAG, TA, TB, TC, F32>(d, st);
 }
 
@@ -796,7 +1017,7 @@ static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
 
 bool zgemm_three_product(const GemmDesc& d) {
   if (d.f32 || (d.tag != KC_POL_CONTRACT && d.tag != KC_SE_CONTRACT)) return false;
-  if (d.cfg < 5 || d.cfg > 9 || (d.M <= 32 && d.N <= 32)) return false;
+  if (d.cfg < 5 || d.cfg > 10 || (d.M <= 32 && d.N <= 32)) return false;
   return uniform_k(d, 4u, d.ta ? 8 : 16, d.tb ? 8 : 16);
 }
 
