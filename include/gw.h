@@ -42,11 +42,11 @@
  * Environment (read by gw_create).  GW_DEBUG_BOUNDS=1 makes every call check
  *   on the host, before launching, that each GEMM descriptor it builds stays
  *   inside the extents of its operands (a failed check returns GW_ERR_ARG);
- *   GW_TILE_CFG=0..10 forces the tile shape of the two large fp64
+ *   GW_TILE_CFG=0..9 forces the tile shape of the two large fp64
  *   contractions (measurement only): 0..4 the four-product complex MFMA form,
- *   5..10 the three-product (Gauss) form, the default (5 for the
- *   polarization, 10 for the self-energy); the Hermitian polarization needs
- *   a square shape: 0, 4 or 5.  GW_PROD_TILES=1 runs the fp32 producers on
+ *   5..9 the three-product (Gauss) form (defaults: 0 for the polarization,
+ *   7 for the self-energy); the Hermitian polarization needs a square shape:
+ *   0, 4 or 5.  GW_PROD_TILES=1 runs the fp32 producers on
  *   the tiled GEMM instead of the streaming kernel (measurement only).
  */
 #ifndef GW_H
@@ -517,8 +517,8 @@ gw_status gw_hermitize(gw_ctx* ctx, gw_z* X, int n, long long nmat);
  * by HIP events recorded on the context's stream; gw_profile_read
  * (synchronises) returns the launch count, the summed event time in ms and
  * the flops those launches execute on the matrix cores: 8 real flops per
- * complex multiply-add, 6 where the fp64 polarization and self-energy
- * contractions use the three-product (Gauss) form, which they do by default;
+ * complex multiply-add, 6 where an fp64 contraction uses the three-product
+ * (Gauss) form (by default the self-energy contraction P~ V);
  * (32/3) n^3 per screened-interaction solve.  Enabling clears the counters. */
 enum { GW_KCLASS_OTHER = 0, GW_KCLASS_POL_CONTRACT = 1, GW_KCLASS_POL_PRODUCER = 2,
        GW_KCLASS_SE_CONTRACT = 3, GW_KCLASS_SE_PRODUCER = 4, GW_KCLASS_SE_FINAL = 5,

@@ -216,11 +216,11 @@ gw_status run(gw_ctx* c, const GemmDesc& g, Ext eA, Ext eB, Ext eC) {
   gw_status s = prof_begin(c, g.tag, &e0);
   if (s != GW_OK) return s;
   GemmDesc gg = g;
-  // tile shapes measured best on MI355X at naux = 250, both on the
-  // three-product (Gauss) form: 64x64 for the polarization contraction,
-  // 64x96 with loads two K-steps ahead for the self-energy one
+  // tile shapes measured best on MI355X at naux = 250: 64x64 for the
+  // polarization contraction, 64x96 on the three-product (Gauss) form for
+  // the self-energy one
   if (g.tag == KC_POL_PRODUCER || g.tag == KC_SE_PRODUCER) gg.cfg = c->prod_tiles;
-  else gg.cfg = c->tile_cfg >= 0 ? c->tile_cfg : (g.tag == KC_SE_CONTRACT ? 10 : 5);
+  else gg.cfg = c->tile_cfg >= 0 ? c->tile_cfg : (g.tag == KC_SE_CONTRACT ? 7 : 0);
   hipError_t e = zgemm_launch(gg, c->st);
   if (e != hipSuccess) return fail(c, GW_ERR_DEVICE, std::string("zgemm: ") + hipGetErrorString(e));
   // MFMA flops executed: 8 real flops per complex multiply-add, 6 on the

@@ -246,12 +246,9 @@ __device__ __forceinline__ float flip(float x, unsigned m) {
 // (Gauss): P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi), then
 // re = P1 - P2 and im = P3 - P1 - P2.  A quarter fewer MFMAs for a third
 // accumulator set; the rounding error stays a few ulps of sum |a| |b|.
-// NB: register stages of the uniform-K loop (2: loads one K-step ahead of the
-// MFMAs, 3: two steps ahead).
 template <int WM, int WN, int WK, int BM, int BN, int TAG, int KM, class TA, class TB, class TC,
-          bool F32, bool G3 = false, int NB = 2>
+          bool F32, bool G3 = false>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
-  static_assert(NB == 2 || NB == 3, "two or three register stages");
   static_assert(!(G3 && F32), "the three-product form is fp64 only");
   constexpr bool M3 = G3 && KM == 2;
   typedef Mfma<F32> MM;
@@ -399,6 +396,12 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     // whose two streamed operands come back from HBM less often with global
     // loads (measured: 100 vs 139 GB fetched per launch, 25.5 vs 27.1 ms).
     constexpr bool LOADG = TAG == KC_POL_CONTRACT;
+    // The fp32 polarization and self-energy contractions (split-K tiles) run
+    // faster with a conditional prefetch that the scheduler interleaves with
+    // the MFMAs (measured at si-4x4x4, ms per q: 18.8 vs 19.7 / 22.1 and 23.0
+    // vs 25.1 / 25.3); every other kernel gains from the branch-free, pinned
+    // one (fp64 polarization 23.8 -> 22.6, fp32 final contraction 6.6 -> 5.4)
+    constexpr bool PIN = !(F32 && (TAG == KC_POL_CONTRACT || TAG == KC_SE_CONTRACT));
     // The four k of a step lie in one aligned group of every K map, so the
     // K offset is one scalar per operand (the buffer soffset) and a lane's
     // byte offset (voffset) is fixed for the whole loop.  Rows past M or N,
@@ -430,9 +433,17 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     bool kvl = true;   // LOADG: this lane's k is below K (only false on the last step)
     Ctr ua = ctr_init(d.ak, kfirst), ub = ctr_init(d.bk, kfirst);
     const unsigned ma = d.conjA ? 0x80000000u : 0u, mb = d.conjB ? 0x80000000u : 0u;
-    auto ldf = [&](S2 (&a)[BM], S2 (&b)[BN]) {
-      const unsigned soa = (unsigned)(ua.off * (long long)sizeof(TA));
-      const unsigned sob = (unsigned)(ub.off * (long long)sizeof(TB));
+    // adv = false: a prefetch past the last full step re-reads the step
+    // loaded last (valid addresses) and leaves the counters where they are.
+    // Selects, not a branch: a load under a branch makes the first use of
+    // any fragment loaded before it wait for all outstanding loads.
+    long long la = ua.off, lb = ub.off;   // K offsets of the step loaded last
+    auto ldf = [&](S2 (&a)[BM], S2 (&b)[BN], bool adv) {
+      const long long oa = adv ? ua.off : la, ob = adv ? ub.off : lb;
+      la = oa;
+      lb = ob;
+      const unsigned soa = (unsigned)(oa * (long long)sizeof(TA));
+      const unsigned sob = (unsigned)(ob * (long long)sizeof(TB));
       if constexpr (LOADG) {
         const char* pa = (const char*)A + soa;
         const char* pb = (const char*)B + sob;
@@ -452,8 +463,15 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
 #pragma unroll
         for (int j = 0; j < BN; ++j) b[j] = MM::cvt(buf_load<TB>(rb, vob[j], sob));
       }
-      ctr_step1(d.ak, ua, kstep);
-      ctr_step1(d.bk, ub, kstep);
+      Ctr na = ua, nb = ub;
+      ctr_step1(d.ak, na, kstep);
+      ctr_step1(d.bk, nb, kstep);
+      ua.off = adv ? na.off : ua.off;
+      ua.a = adv ? na.a : ua.a;
+      ua.b = adv ? na.b : ua.b;
+      ub.off = adv ? nb.off : ub.off;
+      ub.a = adv ? nb.a : ub.a;
+      ub.b = adv ? nb.b : ub.b;
     };
     auto mmf = [&](const S2 (&a)[BM], const S2 (&b)[BN]) {
       S ar[BM], ai[BM], br[BN], bi[BN];
@@ -506,47 +524,26 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
     // steps whose four k are all below K
     const unsigned nfull = kfirst + 4u <= K ? (K - kfirst - 4u) / kstep + 1u : 0u;
     unsigned s = 0;
-    if constexpr (NB == 2) {
-      if (nfull) ldf(a0, b0);
-      for (; s + 2 <= nfull; s += 2) {
-        ldf(a1, b1);
-        mmf(a0, b0);
-        pc(s);
-        if (s + 2 < nfull) ldf(a0, b0);
-        mmf(a1, b1);
-        pc(s + 1);
+    if (nfull) ldf(a0, b0, true);
+    for (; s + 2 <= nfull; s += 2) {
+      ldf(a1, b1, true);
+      // keep each prefetch ahead of the MFMAs it is meant to overlap
+      if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
+      mmf(a0, b0);
+      pc(s);
+      if constexpr (PIN) {
+        ldf(a0, b0, s + 2 < nfull);
+        __builtin_amdgcn_sched_barrier(0);
+      } else if (s + 2 < nfull) {
+        ldf(a0, b0, true);
       }
-      if (s < nfull) {
-        mmf(a0, b0);
-        pc(s);
-        ++s;
-      }
-    } else {
-      // step t lives in buffer t % 3; loads are issued in step order
-      S2 a2[BM], b2[BN];
-      if (nfull > 0) ldf(a0, b0);
-      if (nfull > 1) ldf(a1, b1);
-      for (; s + 3 <= nfull; s += 3) {
-        ldf(a2, b2);
-        mmf(a0, b0);
-        pc(s);
-        if (s + 3 < nfull) ldf(a0, b0);
-        mmf(a1, b1);
-        pc(s + 1);
-        if (s + 4 < nfull) ldf(a1, b1);
-        mmf(a2, b2);
-        pc(s + 2);
-      }
-      if (s < nfull) {
-        mmf(a0, b0);
-        pc(s);
-        ++s;
-      }
-      if (s < nfull) {
-        mmf(a1, b1);
-        pc(s);
-        ++s;
-      }
+      mmf(a1, b1);
+      pc(s + 1);
+    }
+    if (s < nfull) {
+      mmf(a0, b0);
+      pc(s);
+      ++s;
     }
     if (s < nsteps) {
       // last, partial step: lanes with k >= K read zeros
@@ -565,7 +562,7 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
 #pragma unroll
         for (int j = 0; j < BN; ++j) vob[j] = kv ? vob[j] : kOut;
       }
-      ldf(a0, b0);
+      ldf(a0, b0, true);
       mmf(a0, b0);
       pc(s);
     }
@@ -914,7 +911,7 @@ static constexpr size_t residency_lds() {
 }
 
 template <int WM, int WN, int WK, int BM, int BN, int TAG, class TA, class TB, class TC, bool F32,
-          bool G3 = false, int NB = 2>
+          bool G3 = false>
 static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tm_ = (d0.M + TM - 1) / TM;
@@ -933,7 +930,7 @@ static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
   if (F32 && d.kchunk > 0 && d.kchunk % kstep) return hipErrorInvalidValue;
   constexpr int nt = 64 * WM * WN * WK;
   if (uniform_k(d, kstep, sizeof(TA), sizeof(TB)))
-    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32, G3, NB><<<grid, nt, residency_lds<TAG, F32>(), st>>>(d);
+    zgemm_k<WM, WN, WK, BM, BN, TAG, 2, TA, TB, TC, F32, G3><<<grid, nt, residency_lds<TAG, F32>(), st>>>(d);
   else if (one_carry(d.ak, kstep) && one_carry(d.bk, kstep))
     zgemm_k<WM, WN, WK, BM, BN, TAG, 1, TA, TB, TC, F32><<<grid, nt, 0, st>>>(d);
   else
@@ -946,12 +943,12 @@ static hipError_t launch_cfg(const GemmDesc& d0, hipStream_t st) {
 // the configuration in d.cfg
 // (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x64 on eight waves, 4: 64x64 with
 // two-way split K; 5..9 the three-product form on 64x64, 64x128, 64x96,
-// 128x64 on eight waves, 128x64; 10 = 7 with loads two K-steps ahead).
-// Measured at si-4x4x4 (ms per q, fp64): polarization 23.8 (0) vs 22.3 (5),
-// 23.2 with loads two steps ahead; self-energy 31.7 (1) vs 26.0 (7), 25.4
-// (10), 26.7 (5), 28.6 (8), 34.5 (6), 35.2 (9) -- 6 and 9 need more than
-// 256 VGPRs and run one wave per SIMD.  The producers (K = nao) gain nothing
-// from it (11.7 vs 12.0 ms), their stores bound them.
+// 128x64 on eight waves, 128x64).  Measured at si-4x4x4 (ms per q, fp64):
+// polarization 22.6 (0) vs 23.3 (5), 28.0 (4); self-energy 31.7 (1) vs 25.7
+// (7), 27.2 (5), 28.6 (8), 34.5 (6), 35.2 (9) -- 6 and 9 need more than 256
+// VGPRs and run one wave per SIMD; loads two K-steps ahead (a third register
+// stage) gained nothing on either.  The producers (K = nao) gain nothing
+// from the three-product form (11.7 vs 12.0 ms), their stores bound them.
 template <int TAG, class TA, class TB, class TC, bool F32>
 static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
   if (d.M <= 32 && d.N <= 32) return launch_cfg<1, 1, 4, 2, 2, TAG, TA, TB, TC, F32>(d, st);
@@ -966,7 +963,6 @@ static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
       case 7: return launch_cfg<2, 2, 1, 2, 3, TAG, TA, TB, TC, F32, true>(d, st);
       case 8: return launch_cfg<4, 2, 1, 2, 2, TAG, TA, TB, TC, F32, true>(d, st);
       case 9: return launch_cfg<2, 2, 1, 4, 2, TAG, TA, TB, TC, F32, true>(d, st);
-      case 10: return launch_cfg<2, 2, 1, 2, 3, TAG, TA, TB, TC, F32, true, 3>(d, st);
       default: break;
     }
   }
@@ -1017,7 +1013,7 @@ static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
 
 bool zgemm_three_product(const GemmDesc& d) {
   if (d.f32 || (d.tag != KC_POL_CONTRACT && d.tag != KC_SE_CONTRACT)) return false;
-  if (d.cfg < 5 || d.cfg > 10 || (d.M <= 32 && d.N <= 32)) return false;
+  if (d.cfg < 5 || d.cfg > 9 || (d.M <= 32 && d.N <= 32)) return false;
   return uniform_k(d, 4u, d.ta ? 8 : 16, d.tb ? 8 : 16);
 }
 
