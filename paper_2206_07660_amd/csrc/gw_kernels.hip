@@ -1068,20 +1068,29 @@ template <> struct Chunk<double2> { double2 v[8]; };
 
 // loads 8 consecutive k (stride ks elements, 1 if CONTIG) from p; k >= K
 // gives zeros
+// A chunk whose eight k all lie below K: no branch, so that the loads of the
+// next K-step stay in flight while the MFMAs of the current one run (a
+// branch around them makes the compiler wait for them at once).
+template <bool CONTIG, class T>
+__device__ __forceinline__ void load_chunk_full(Chunk<T>& c, const T* p, long long ks, int k0) {
+  if constexpr (CONTIG) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) c.v[e] = p[k0 + e];
+  } else {
+    // byte stride as a wave-uniform 32-bit value: the eight addresses are
+    // scalar offsets from one per-lane pointer
+    const unsigned sb = __builtin_amdgcn_readfirstlane((unsigned)(ks * (long long)sizeof(T)));
+    const char* q = (const char*)(p + (long long)k0 * ks);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) c.v[e] = *(const T*)(q + (unsigned)e * sb);
+  }
+}
+
+// Any chunk (the last, partial K-step): k past K reads zeros.
 template <bool CONTIG, class T>
 __device__ __forceinline__ void load_chunk(Chunk<T>& c, const T* p, long long ks, int k0, int K) {
   if (k0 + 8 <= K) {
-    if constexpr (CONTIG) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) c.v[e] = p[k0 + e];
-    } else {
-      // byte stride as a wave-uniform 32-bit value: the eight addresses are
-      // scalar offsets from one per-lane pointer
-      const unsigned sb = __builtin_amdgcn_readfirstlane((unsigned)(ks * (long long)sizeof(T)));
-      const char* q = (const char*)(p + (long long)k0 * ks);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) c.v[e] = *(const T*)(q + (unsigned)e * sb);
-    }
+    load_chunk_full<CONTIG>(c, p, ks, k0);
   } else {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -1170,6 +1179,12 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
 #pragma unroll
     for (int u = 0; u < CB; ++u) load_chunk<BK1>(cb[u], pb[u], d.bks, 32 * s + 8 * kb[u], d.K);
   };
+  auto fetch_full = [&](int s) {
+#pragma unroll
+    for (int u = 0; u < CA; ++u) load_chunk_full<AK1>(ca[u], pa[u], d.aks, 32 * s + 8 * ka[u]);
+#pragma unroll
+    for (int u = 0; u < CB; ++u) load_chunk_full<BK1>(cb[u], pb[u], d.bks, 32 * s + 8 * kb[u]);
+  };
   auto stash = [&](int stage) {
     unsigned char* base = lds + stage * STAGE;
 #pragma unroll
@@ -1256,13 +1271,23 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
   };
 
   // step t's chunks live in LDS stage t % 2; the loads of step s + 1 are
-  // issued before the MFMAs of step s
-  const int nsteps = (d.K + 31) / 32;
+  // issued before the MFMAs of step s.  The main loop prefetches only full
+  // K-steps (no branch around the loads); the partial last step, if any,
+  // goes through the second loop.
+  const int nsteps = (d.K + 31) / 32, nfull = d.K / 32;
   const int cper = d.kchunk / 32;
   fetch(0);
   stash(0);
   __syncthreads();
-  for (int s = 0; s < nsteps; ++s) {
+  int s = 0;
+  for (; s + 1 < nfull; ++s) {
+    fetch_full(s + 1);
+    compute(s & 1);
+    stash((s + 1) & 1);
+    if ((s + 1) % cper == 0) promote();
+    __syncthreads();
+  }
+  for (; s < nsteps; ++s) {
     if (s + 1 < nsteps) fetch(s + 1);
     compute(s & 1);
     if (s + 1 < nsteps) stash((s + 1) & 1);
