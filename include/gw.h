@@ -46,8 +46,12 @@
  *   contractions (measurement only): 0..4 the four-product complex MFMA form,
  *   5..9 the three-product (Gauss) form (defaults: 0 for the polarization,
  *   7 for the self-energy); the Hermitian polarization needs a square shape:
- *   0, 4 or 5.  GW_PROD_TILES=1 runs the fp32 producers on
- *   the tiled GEMM instead of the streaming kernel (measurement only).
+ *   0, 4 or 5.  GW_PROD_TILES=1 runs the fp32 producers on the tiled GEMM
+ *   instead of the streaming kernel.  GW_SPLIT_CFG selects split-bf16 tiles:
+ *   bf16x3 self-energy 0 = 128x128 (default), 1 = 64x64, 2 = 128x64; bf16x6
+ *   1 = two LDS stages instead of one.  GW_SPLIT_GROUP=g > 0 walks the
+ *   split-bf16 tiles in groups of g over the tau batch.  All of these are
+ *   for measurement only.
  */
 #ifndef GW_H
 #define GW_H

@@ -1134,14 +1134,15 @@ __device__ __forceinline__ void put_chunk(const Chunk<T>& c, unsigned char* row,
 }
 
 template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
-          class SUMT, int NS>
+          class SUMT, int NS, int NSTG = 2>
 __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
+  static_assert(NSTG == 1 || NSTG == 2, "one or two LDS stages");
   constexpr int kRowB = row_bytes<NS>();
   constexpr int NT = 64 * WM * WN, TM = WM * BM * 16, TN = WN * BN * 16;
   constexpr int CA = TM * 4 / NT, CB = TN * 4 / NT;   // loader chunks per thread
   static_assert(CA >= 1 && CB >= 1 && CA * NT == TM * 4 && CB * NT == TN * 4, "loader split");
   constexpr int STAGE = (TM + TN) * kRowB;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[NSTG * STAGE];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1280,17 +1281,22 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
   stash(0);
   __syncthreads();
   int s = 0;
+  // one LDS stage: the next step's chunks wait in registers until every wave
+  // has read the stage (a second barrier per step, half the LDS)
+  auto stg = [](int t) { return NSTG == 2 ? (t & 1) : 0; };
   for (; s + 1 < nfull; ++s) {
     fetch_full(s + 1);
-    compute(s & 1);
-    stash((s + 1) & 1);
+    compute(stg(s));
+    if constexpr (NSTG == 1) __syncthreads();
+    stash(stg(s + 1));
     if ((s + 1) % cper == 0) promote();
     __syncthreads();
   }
   for (; s < nsteps; ++s) {
     if (s + 1 < nsteps) fetch(s + 1);
-    compute(s & 1);
-    if (s + 1 < nsteps) stash((s + 1) & 1);
+    compute(stg(s));
+    if constexpr (NSTG == 1) __syncthreads();
+    if (s + 1 < nsteps) stash(stg(s + 1));
     if ((s + 1) % cper == 0) promote();
     __syncthreads();
   }
@@ -1336,7 +1342,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bsgemm_k(SplitDesc d) {
 }
 
 template <int WM, int WN, int BM, int BN, int TAG, class TA, class TB, class TC, bool SUMS, bool AK1, bool BK1,
-          class SUMT, int NS>
+          class SUMT, int NS, int NSTG = 2>
 static hipError_t bs_cfg(const SplitDesc& d0, hipStream_t st) {
   constexpr int TM = WM * BM * 16, TN = WN * BN * 16;
   const long long tm_ = (d0.M + TM - 1) / TM;
@@ -1350,7 +1356,7 @@ static hipError_t bs_cfg(const SplitDesc& d0, hipStream_t st) {
   d.q_tiles = udiv_make((unsigned)tiles);
   d.q_batch = udiv_make((unsigned)d.batch);
   if ((d0.aks == 1) != AK1 || (d0.bks == 1) != BK1) return hipErrorInvalidValue;
-  bsgemm_k<WM, WN, BM, BN, TAG, TA, TB, TC, SUMS, AK1, BK1, SUMT, NS><<<dim3((unsigned)(tiles * d.batch)), 64 * WM * WN, 0, st>>>(d);
+  bsgemm_k<WM, WN, BM, BN, TAG, TA, TB, TC, SUMS, AK1, BK1, SUMT, NS, NSTG><<<dim3((unsigned)(tiles * d.batch)), 64 * WM * WN, 0, st>>>(d);
   return hipGetLastError();
 }
 
@@ -1371,13 +1377,23 @@ hipError_t bsgemm_launch(const SplitDesc& d, hipStream_t st) {
   // K = Q' with stride n2
   if (d.nsplit == 3) {
     // bf16x6: fp64 chunk sums (the products are as accurate as fp32 ones);
-    // 64 x 64 tiles, as 128 x 128 ones would need 205 KB of LDS
-    if (d.tag == KC_POL_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 0)
-      return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, double, 3>(d, st);
+    // 64 x 64 tiles, as 128 x 128 ones would need 205 KB of LDS with two
+    // stages, and the loader needs at least one chunk of each operand per
+    // thread
+    // One LDS stage (51 KB) lets two workgroups share a CU where two stages
+    // (102 KB) allow one: 8.7 vs 9.8 ms (polarization) and 14.3 vs 22.1 ms
+    // (self-energy) per q at si-4x4x4.  d.cfg = 1 selects two stages.
+    if (d.tag == KC_POL_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 0) {
+      if (d.cfg == 1)
+        return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, double, 3>(d, st);
+      return bs_cfg<2, 2, 2, 2, KC_POL_CONTRACT, float2, float2, double2, true, true, true, double, 3, 1>(d, st);
+    }
     if (d.tag == KC_SE_CONTRACT && d.ta == 1 && d.tb == 1 && d.tc == 1) {
       if (d.K > d.kchunk)
-        return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false, double, 3>(d, st);
-      return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, double, 3>(d, st);
+        return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, true, true, false, double, 3, 1>(d, st);
+      if (d.cfg == 1)
+        return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, double, 3>(d, st);
+      return bs_cfg<2, 2, 2, 2, KC_SE_CONTRACT, float2, float2, float2, false, true, false, double, 3, 1>(d, st);
     }
     return hipErrorInvalidValue;
   }
