@@ -1201,7 +1201,11 @@ gw_status gw_self_energy(gw_ctx* c, const void* V, const gw_z* G, const gw_z* Pt
         else { g.cm = aff((long long)nk * n2); g.cn = aff(1); }
         g.ba = aff((long long)naux * naux); g.bb = aff(0); g.bc = aff(S);
         g.ta = 0; g.tb = g.tc = t; g.f32 = t;
-        g.batch_fastest = 1;                      // every tau reads the same V slab
+        // groups of 8 tiles walk every tau: their V tiles and each tau's P~
+        // panels stay in L2 (measured at si-4x4x4: fetch 49 -> 29 GB per q,
+        // 25.6 vs 25.9 ms; groups of 16: 21 GB, 26.1 ms)
+        g.batch_fastest = 2;
+        g.group = 8;
         g.tag = KC_SE_CONTRACT;
         gw_status s = run(c, g, Ext{0, (long long)tcur * naux * naux}, Ext{0, (long long)nk * sv}, Ext{0, (long long)tcur * S});
         if (s != GW_OK) return s;
