@@ -521,8 +521,9 @@ gw_status gw_hermitize(gw_ctx* ctx, gw_z* X, int n, long long nmat);
  * by HIP events recorded on the context's stream; gw_profile_read
  * (synchronises) returns the launch count, the summed event time in ms and
  * the flops those launches execute on the matrix cores: 8 real flops per
- * complex multiply-add, 6 where an fp64 contraction uses the three-product
- * (Gauss) form (by default the self-energy contraction P~ V);
+ * complex multiply-add, 6 where a contraction uses the three-product
+ * (Gauss) form (by default the self-energy contraction P~ V in fp64 and in
+ * GW_PREC_FP32);
  * (32/3) n^3 per screened-interaction solve.  Enabling clears the counters. */
 enum { GW_KCLASS_OTHER = 0, GW_KCLASS_POL_CONTRACT = 1, GW_KCLASS_POL_PRODUCER = 2,
        GW_KCLASS_SE_CONTRACT = 3, GW_KCLASS_SE_PRODUCER = 4, GW_KCLASS_SE_FINAL = 5,

@@ -242,14 +242,14 @@ __device__ __forceinline__ float flip(float x, unsigned m) {
 // KM: K-loop form.  0 general index maps (any number of carries per step);
 // 1 at most one carry per digit and step; 2 "uniform" (see launch_cfg): the
 // K offset is a wave-uniform scalar and each lane keeps a constant offset.
-// G3 (fp64, uniform-K loop): the complex product on three real MFMAs
-// (Gauss): P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi), then
-// re = P1 - P2 and im = P3 - P1 - P2.  A quarter fewer MFMAs for a third
-// accumulator set; the rounding error stays a few ulps of sum |a| |b|.
+// G3 (uniform-K loop): the complex product on three real MFMAs (Gauss):
+// P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi), then
+// re = P1 - P2 and im = P3 - P1 - P2 (with F32 at every fp64 promotion).  A
+// quarter fewer MFMAs for a third accumulator set; the rounding error stays
+// a few ulps of sum |a| |b|.
 template <int WM, int WN, int WK, int BM, int BN, int TAG, int KM, class TA, class TB, class TC,
           bool F32, bool G3 = false>
 __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
-  static_assert(!(G3 && F32), "the three-product form is fp64 only");
   constexpr bool M3 = G3 && KM == 2;
   typedef Mfma<F32> MM;
   typedef typename MM::S S;
@@ -314,11 +314,18 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
         for (int j = 0; j < BN; ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            sumR[i][j][r] += (double)accR[i][j][r];
-            sumI[i][j][r] += (double)accI[i][j][r];
+            if constexpr (M3) {
+              const double p1 = accR[i][j][r], p2 = accN[i][j][r], p3 = accI[i][j][r];
+              sumR[i][j][r] += p1 - p2;
+              sumI[i][j][r] += p3 - p1 - p2;
+            } else {
+              sumR[i][j][r] += (double)accR[i][j][r];
+              sumI[i][j][r] += (double)accI[i][j][r];
+            }
           }
           accR[i][j] = Acc{0, 0, 0, 0};
           accI[i][j] = Acc{0, 0, 0, 0};
+          if constexpr (M3) accN[i][j] = Acc{0, 0, 0, 0};
         }
     }
   };
@@ -588,7 +595,7 @@ __global__ void __launch_bounds__(64 * WM * WN * WK) zgemm_k(GemmDesc d) {
 
   // lane-local result, fp64
   auto res = [&](int i, int j, int r, bool im) -> double {
-    if constexpr (F32) return im ? sumI[i][j][r] : sumR[i][j][r];
+    if constexpr (F32) return im ? sumI[i][j][r] : sumR[i][j][r];   // M3 combined in promote
     else if constexpr (M3)
       return im ? accI[i][j][r] - accR[i][j][r] - accN[i][j][r] : accR[i][j][r] - accN[i][j][r];
     else return im ? accI[i][j][r] : accR[i][j][r];
@@ -969,8 +976,14 @@ static hipError_t launch_typed(const GemmDesc& d, hipStream_t st) {
   // fp32 MFMA steps are half as long, so the two large contractions split K
   // over two waves per output block (64 x 64, 8 waves): measured 19.2 vs
   // 20.5 ms (polarization) and 22.6 vs 26.0 ms (self-energy) per q
-  if constexpr ((TAG == KC_POL_CONTRACT || TAG == KC_SE_CONTRACT) && F32)
+  // The product form follows d.cfg (5..9: three products), the tile does
+  // not: the fp32 self-energy contraction (default 7) runs three products,
+  // 19.9-20.3 vs 23.1 ms per q, the polarization one (default 0) four, 19.1
+  // vs 19.9 ms.
+  if constexpr ((TAG == KC_POL_CONTRACT || TAG == KC_SE_CONTRACT) && F32) {
+    if (d.cfg >= 5 && d.cfg <= 9) return launch_cfg<2, 2, 2, 2, 2, TAG, TA, TB, TC, F32, true>(d, st);
     return launch_cfg<2, 2, 2, 2, 2, TAG, TA, TB, TC, F32>(d, st);
+  }
   // the producers (K = nao): fp32 MFMA (complex64 intermediates) on the
   // streaming kernel (measured 7.7 vs 8.2 ms per polarization call and 3.8
   // vs 4.0 ms per self-energy producer at si-4x4x4); fp64 on 64 x 128 tiles,
@@ -1012,9 +1025,10 @@ static hipError_t launch_tag(const GemmDesc& d, hipStream_t st) {
 }
 
 bool zgemm_three_product(const GemmDesc& d) {
-  if (d.f32 || (d.tag != KC_POL_CONTRACT && d.tag != KC_SE_CONTRACT)) return false;
+  if (d.tag != KC_POL_CONTRACT && d.tag != KC_SE_CONTRACT) return false;
   if (d.cfg < 5 || d.cfg > 9 || (d.M <= 32 && d.N <= 32)) return false;
-  return uniform_k(d, 4u, d.ta ? 8 : 16, d.tb ? 8 : 16);
+  // the fp32 tile splits K over two waves: K-steps of 8
+  return uniform_k(d, d.f32 ? 8u : 4u, d.ta ? 8 : 16, d.tb ? 8 : 16);
 }
 
 hipError_t zgemm_launch(const GemmDesc& d, hipStream_t st) {
